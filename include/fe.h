@@ -1,0 +1,252 @@
+/*
+ * fe.h -- modified no-search (MNS) fractal image encoder for AMD gfx950.
+ *
+ * C ABI of libfe.so.  Every entry point takes plain pointers and sizes; no
+ * C++ or framework types cross it, no exception escapes it, and every call
+ * returns an fe_status.  After a failure, fe_last_error() returns a short
+ * text for the calling thread.
+ *
+ * The method is the one of "A Modified No Search Algorithm for Fractal Image
+ * Compression" (Salarian, Mohamadinia, Rasekhi):
+ *   - an image is cut into B x B range blocks; each range is matched against
+ *     the single 2B x 2B domain block with the same centre, reduced to B x B
+ *     by the mean of every 2 x 2 pixel group (Sec. 3, Fig. 1b);
+ *   - only a contrast s and a luminance are fitted; the range is stored if
+ *     its error is below the level's threshold or the level is the last one,
+ *     otherwise it is split into four (Sec. 3, quadtree);
+ *   - ranges that fail get a second phase (Sec. 3.1 Technique 1, Sec. 3.2):
+ *     if every sub-block mean is close to the range mean, each sub-block is
+ *     fitted with one of two level-dependent contrasts, and the range is
+ *     stored with its mean, three sub-block means (the fourth follows from
+ *     eq. (1), Sec. 3.3) and one contrast bit per sub-block;
+ *   - decoding iterates the stored contractive maps from any start image
+ *     (Sec. 1).
+ * The exhaustive search that no-search replaces (Sec. 1: every step-1
+ * domain, (W-2B+1)(H-2B+1) candidates per range) is provided as a baseline.
+ *
+ * Arithmetic.  All encoder arithmetic is exact integer arithmetic.  With
+ * n = B^2, Sum r, Sum r^2, Sum d, Sum d^2 and Sum r T_e(d) for the 8 square
+ * isometries e, Q = n Sum d^2 - (Sum d)^2, R = n Sum r^2 - (Sum r)^2 and
+ * P_e = n Sum r T_e(d) - Sum r Sum d, a phase-1 fit with contrast k/8
+ * (k = 0..7) and luminance m (the range mean rounded half up) has the scaled
+ * collage error S = k^2 Q - 16 k P_e + 64 R + 64 (n m - Sum r)^2 = 64 n E,
+ * E = sum over the block of (prediction - pixel)^2 with prediction
+ * (k/8)(T_e(d) - mean d) + m.  The best (e, k) minimises S (lowest e, then
+ * lowest k on ties).  A range at level l is accepted when S < 64 n^2 t_l,
+ * i.e. its MSE is below the integer threshold t_l.
+ *
+ * Memory.  Pointers named d_* are device pointers (any HIP allocation on the
+ * context's device, e.g. a torch tensor's data_ptr()); h_* are host
+ * pointers.  The caller owns every input and output buffer; the library
+ * owns only its internal scratch, held by the fe_ctx and released by
+ * fe_destroy.  `stream` is a hipStream_t (NULL = the null stream); work is
+ * enqueued on it and, unless a call says otherwise, the call returns
+ * without waiting.  One fe_ctx must not be used by two threads at once, and
+ * calls that share one fe_ctx must be issued on one stream (they share its
+ * scratch).
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fe_status {
+  FE_OK = 0,
+  FE_ERR_INVALID = 1,   /* a parameter is out of range or a pointer is NULL */
+  FE_ERR_SHAPE = 2,     /* image sides / stride / alignment do not fit the block sizes */
+  FE_ERR_CAPACITY = 3,  /* output too small; the needed count is reported */
+  FE_ERR_DEVICE = 4,    /* a HIP call failed or no usable gfx950 device */
+  FE_ERR_OOM = 5,       /* device or pinned host allocation failed */
+  FE_ERR_BUSY = 6       /* a queue or slot limit was reached; retry later */
+} fe_status;
+
+/*
+ * One stored transform, 16 bytes, little-endian, every byte defined (two
+ * equal streams are equal byte for byte).
+ *
+ *   x, y      range top-left corner in pixels.
+ *   dx, dy    domain origin in pixels: for MNS the co-centred origin
+ *             clamp(x - B/2, 0, W - 2B) (likewise dy), for the exhaustive
+ *             search the chosen step-1 origin (any parity).  A phase-2
+ *             record holds the co-centred origin of the whole range; each
+ *             of its sub-blocks uses its own co-centred domain of size B.
+ *   level     0-based quadtree level: B = b_max >> level.
+ *   flags     bit 0 (FE_TRANSFORM_PHASE2): phase-2 record (Sec. 3.1).
+ *   iso       phase 1: isometry 0..7 applied to the domain before the fit:
+ *             0 identity, 1 mirror left-right, 2 mirror top-bottom,
+ *             3 rotate 180, 4 transpose, 5 rotate 90 clockwise,
+ *             6 rotate 90 counter-clockwise, 7 anti-transpose
+ *             (T_e(d)[i][j] = d[i][j], d[i][B-1-j], d[B-1-i][j],
+ *             d[B-1-i][B-1-j], d[j][i], d[B-1-j][i], d[j][B-1-i],
+ *             d[B-1-j][B-1-i]).  Phase 2: 0.
+ *   s_idx     phase 1: k, contrast s = k/8 (three bits, Sec. 3.3).
+ *             Phase 2: bit c set -> sub-block c uses the second contrast of
+ *             the level's set {.2,.5}, {.4,.65}, {.5,.9} for levels 1, 2, 3
+ *             (Sec. 3.2); sub-blocks c = 0..3 are top-left, top-right,
+ *             bottom-left, bottom-right.
+ *   lum       phase 1: luminance m, the range mean rounded half up (one
+ *             byte, Sec. 3.3).  Phase 2: the range mean O_i.
+ *   dlum      phase 2: O_c - O_i for sub-blocks c = 0, 1, 2, within
+ *             +-15 at level 1 and +-31 at levels 2 and 3 (5 and 6 bits
+ *             with sign, Sec. 3.3); O_3 = 4 O_i - O_0 - O_1 - O_2 (eq. (1)).
+ *             Zero in phase 1.
+ *
+ * A stream lists the transforms of one image in depth-first order: top
+ * tiles in raster order, and inside a tile the quadtree in pre-order with
+ * children top-left, top-right, bottom-left, bottom-right.
+ */
+typedef struct fe_transform {
+  uint16_t x, y;
+  uint16_t dx, dy;
+  uint8_t level;
+  uint8_t flags;
+  uint8_t iso;
+  uint8_t s_idx;
+  uint8_t lum;
+  int8_t dlum[3];
+} fe_transform;
+
+#define FE_TRANSFORM_PHASE2 1u
+
+/* fe_params.flags */
+#define FE_PHASE2 1u       /* run Technique 1 on ranges that fail (MNS); off = plain no-search */
+#define FE_FULL_SEARCH 2u  /* exhaustive step-1 search (Sec. 1) instead of the co-centred domain; no phase 2 */
+
+/*
+ * Encoder parameters.
+ *   b_max, b_min  largest and smallest range side: powers of two with
+ *                 4 <= b_min <= b_max <= 32 (at most four levels, Sec. 3.3).
+ *   n_thr         number of thresholds = L - 1, L = log2(b_max/b_min) + 1.
+ *   flags         FE_PHASE2 and/or FE_FULL_SEARCH.
+ *   mse_thr[l-1]  integer MSE threshold t_l of level l = 1..L-1 (the last
+ *                 level is always stored, Sec. 3); unused entries ignored.
+ */
+typedef struct fe_params {
+  uint32_t b_max;
+  uint32_t b_min;
+  uint32_t n_thr;
+  uint32_t flags;
+  uint32_t mse_thr[4];
+} fe_params;
+
+/* One image of a batch: device pointer, sides, row pitch in bytes. */
+typedef struct fe_image_desc {
+  const uint8_t* data;
+  uint32_t width;
+  uint32_t height;
+  uint32_t stride;
+  uint32_t reserved; /* must be 0 */
+} fe_image_desc;
+
+typedef struct fe_ctx fe_ctx;
+
+/* Text of the last failure on this thread ("" if none).  Valid until the
+ * thread's next fe_* call. */
+const char* fe_last_error(void);
+
+/* Static name of a status code. */
+const char* fe_status_string(fe_status status);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int fe_version(void);
+
+/*
+ * Host-only check of an encode request (no device needed).  FE_ERR_INVALID
+ * for bad block sizes, thresholds count or flags; FE_ERR_SHAPE when W or H
+ * is not a multiple of b_max, smaller than 2 b_max (the domain of every
+ * range must fit), larger than 65536, or stride < W, or stride not a
+ * multiple of 4.
+ */
+fe_status fe_validate(uint32_t width, uint32_t height, uint32_t stride, const fe_params* params);
+
+/* Upper bound of the stream length of one W x H image:
+ * (W / b_min) * (H / b_min); 0 if b_min is 0. */
+size_t fe_max_transforms(uint32_t width, uint32_t height, uint32_t b_min);
+
+/*
+ * Open a context on HIP device `device` (must be gfx950).  FE_ERR_DEVICE
+ * when there is no such device.  The context owns scratch memory that grows
+ * with the largest request seen and is freed by fe_destroy.
+ */
+fe_status fe_create(int device, fe_ctx** out);
+void fe_destroy(fe_ctx* ctx);
+
+/*
+ * Domain pyramid level used by no-search (Sec. 3: "mean filter to four
+ * neighbor pixels"): d_out[j * (W/2) + i] = (I[2j][2i] + I[2j][2i+1] +
+ * I[2j+1][2i] + I[2j+1][2i+1] + 2) >> 2, a dense (H/2) x (W/2) uint8 image.
+ * W and H even and >= 2; stride >= W, multiple of 4; d_img 4-byte aligned.
+ */
+fe_status fe_downsample(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t height,
+                        uint32_t stride, uint8_t* d_out, void* stream);
+
+/*
+ * Moments of explicit ranges against their co-centred domains (the moment
+ * step of Sec. 3).  Range i of side `block` (4, 8, 16 or 32) has top-left
+ * corner x = d_xy[i] & 0xffff, y = d_xy[i] >> 16 (multiples of `block`,
+ * inside the image); the image must satisfy fe_validate for b_max = block.
+ * Writes 12 uint32 per range to d_moments[12 i ..]: Sum r, Sum r^2, Sum d,
+ * Sum d^2, then Sum r T_e(d) for e = 0..7, where d is the domain reduced to
+ * block x block.  Out-of-image ranges give FE_ERR_INVALID before any launch
+ * only if detectable on the host; the device skips them (moments left 0).
+ */
+fe_status fe_range_moments(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t height,
+                           uint32_t stride, uint32_t block, const uint32_t* d_xy, uint32_t count,
+                           uint32_t* d_moments, void* stream);
+
+/*
+ * Encode one image (MNS, Sec. 3 and 3.1-3.3; or the exhaustive baseline
+ * with FE_FULL_SEARCH).  d_img is W x H uint8 with row pitch `stride`
+ * bytes (4-byte aligned).  Writes the stream to d_out[0 .. *n_out).
+ * Waits for the stream to finish (the count is needed on the host).
+ * FE_ERR_CAPACITY if cap is smaller than the stream; *n_out then holds
+ * the needed count and d_out is left unspecified.  cap =
+ * fe_max_transforms(W, H, b_min) always suffices.
+ */
+fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t height,
+                    uint32_t stride, const fe_params* params, fe_transform* d_out, size_t cap,
+                    size_t* n_out, void* stream);
+
+/*
+ * Encode a batch of images of any sides in one pass (one launch covers
+ * every range of every image).  Image k's stream is written to
+ * d_out[d_offsets[k] .. d_offsets[k+1]); d_offsets (device, n_imgs + 1
+ * entries) is written by the device.  If n_out is not NULL the call waits
+ * and stores the total count (FE_ERR_CAPACITY as for fe_encode); if it is
+ * NULL the call returns at once and the caller must check
+ * d_offsets[n_imgs] <= cap itself (entries beyond cap are not written).
+ * FE_FULL_SEARCH is not accepted here.
+ */
+fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
+                          const fe_params* params, fe_transform* d_out, size_t cap,
+                          uint64_t* d_offsets, size_t* n_out, void* stream);
+
+/*
+ * Decode (Sec. 1): start from d_start (W x H, dense) or mid-grey 128 if
+ * d_start is NULL, and apply the n transforms `iters` times; every
+ * iteration computes all pixels from the previous iterate (Jacobi).  A
+ * phase-1 transform writes, for each pixel p of its range,
+ *   clamp(floor((k (n d_p - Sum d) + 8 n m + 4 n) / (8 n)), 0, 255),
+ * with d the 2 x 2 round-half-up means of the current iterate over the 2B x
+ * 2B block at (dx, dy), taken under the isometry; a phase-2 transform does
+ * the same for each sub-block with contrast c/20, its own co-centred domain
+ * and luminance O_c.  The stream must tile the image; pixels it does not
+ * cover keep the start value.  Writes the W x H result to d_out (dense).
+ * Checks every transform on the device first and returns FE_ERR_INVALID
+ * (and leaves d_out unspecified) if one is out of range; waits for that
+ * check.
+ */
+fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t width,
+                    uint32_t height, uint32_t b_max, uint32_t iters, const uint8_t* d_start,
+                    uint8_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

@@ -1,0 +1,265 @@
+"""ctypes binding of libfe.so: argument marshalling only.
+
+Every function mirrors the C entry point of the same name in include/fe.h.
+Device buffers are torch tensors on the context's GPU (PyTorch supplies
+memory and streams); every step of the method runs in the library's HIP
+kernels.  If libfe.so is missing or cannot be loaded, every call raises:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfe.so")
+
+FE_OK, FE_ERR_INVALID, FE_ERR_SHAPE, FE_ERR_CAPACITY, FE_ERR_DEVICE, FE_ERR_OOM, FE_ERR_BUSY = range(7)
+FE_PHASE2 = 1
+FE_FULL_SEARCH = 2
+FE_TRANSFORM_PHASE2 = 1
+
+# 16-byte transform layout of include/fe.h (little-endian).
+TRANSFORM_DTYPE = np.dtype([
+    ("x", "<u2"), ("y", "<u2"), ("dx", "<u2"), ("dy", "<u2"),
+    ("level", "u1"), ("flags", "u1"), ("iso", "u1"), ("s_idx", "u1"),
+    ("lum", "u1"), ("dlum", "i1", (3,)),
+])
+assert TRANSFORM_DTYPE.itemsize == 16
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_STATUS_NAMES = {0: "FE_OK", 1: "FE_ERR_INVALID", 2: "FE_ERR_SHAPE", 3: "FE_ERR_CAPACITY",
+                 4: "FE_ERR_DEVICE", 5: "FE_ERR_OOM", 6: "FE_ERR_BUSY"}
+
+
+class fe_params(ctypes.Structure):
+    _fields_ = [("b_max", ctypes.c_uint32), ("b_min", ctypes.c_uint32), ("n_thr", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("mse_thr", ctypes.c_uint32 * 4)]
+
+
+class fe_image_desc(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes)
+_SIGNATURES = {
+    "fe_last_error": (ctypes.c_char_p, []),
+    "fe_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fe_version": (ctypes.c_int, []),
+    "fe_validate": (ctypes.c_int, [_U32, _U32, _U32, ctypes.POINTER(fe_params)]),
+    "fe_max_transforms": (_SZ, [_U32, _U32, _U32]),
+    "fe_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP)]),
+    "fe_destroy": (None, [_VP]),
+    "fe_downsample": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _VP, _VP]),
+    "fe_range_moments": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
+    "fe_encode": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params), _VP, _SZ,
+                                 ctypes.POINTER(_SZ), _VP]),
+    "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
+                                       _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
+    "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libfe.so (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1501_02894_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols(header: str) -> list[str]:
+    """Names of the functions include/fe.h declares."""
+    import re
+    text = open(header).read()
+    return sorted(set(re.findall(r"\b(fe_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != FE_OK:
+        msg = load().fe_last_error().decode(errors="replace")
+        raise FeError(status, msg)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def make_params(b_max: int, b_min: int, thresholds, phase2: bool = True, full_search: bool = False) -> fe_params:
+    p = fe_params()
+    p.b_max, p.b_min = int(b_max), int(b_min)
+    thr = [int(t) for t in thresholds]
+    p.n_thr = len(thr)
+    p.flags = (FE_PHASE2 if phase2 else 0) | (FE_FULL_SEARCH if full_search else 0)
+    for i, t in enumerate(thr[:4]):
+        p.mse_thr[i] = t
+    return p
+
+
+# ------------------------------------------------------------------ C names
+def fe_version() -> int:
+    return int(load().fe_version())
+
+
+def fe_validate(width: int, height: int, stride: int, params: fe_params) -> int:
+    return int(load().fe_validate(width, height, stride, ctypes.byref(params)))
+
+
+def fe_max_transforms(width: int, height: int, b_min: int) -> int:
+    return int(load().fe_max_transforms(width, height, b_min))
+
+
+def fe_create(device: int = 0) -> int:
+    h = _VP()
+    _check(load().fe_create(int(device), ctypes.byref(h)))
+    return h.value
+
+
+def fe_destroy(ctx: int) -> None:
+    load().fe_destroy(ctx)
+
+
+def fe_downsample(ctx: int, img, out=None, stream=None):
+    import torch
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H // 2, W // 2), dtype=torch.uint8, device=img.device)
+    _check(load().fe_downsample(ctx, _ptr(img), W, H, img.stride(0), _ptr(out), _stream(stream)))
+    return out
+
+
+def fe_range_moments(ctx: int, img, block: int, xy, out=None, stream=None):
+    """xy: int32 tensor of packed x | y << 16; returns (count, 12) int32
+    tensor holding the uint32 moments."""
+    import torch
+    H, W = img.shape
+    count = int(xy.numel())
+    if out is None:
+        out = torch.zeros((count, 12), dtype=torch.int32, device=img.device)
+    _check(load().fe_range_moments(ctx, _ptr(img), W, H, img.stride(0), int(block), _ptr(xy), count,
+                                   _ptr(out), _stream(stream)))
+    return out
+
+
+def fe_encode(ctx: int, img, params: fe_params, out=None, stream=None):
+    """Returns a (n, 16) uint8 device tensor (view of `out`)."""
+    import torch
+    H, W = img.shape
+    cap = fe_max_transforms(W, H, params.b_min)
+    if out is None:
+        out = torch.empty((cap, 16), dtype=torch.uint8, device=img.device)
+    n = _SZ(0)
+    _check(load().fe_encode(ctx, _ptr(img), W, H, img.stride(0), ctypes.byref(params), _ptr(out),
+                            out.shape[0], ctypes.byref(n), _stream(stream)))
+    return out[: n.value]
+
+
+def fe_encode_batch(ctx: int, imgs, params: fe_params, out=None, offsets=None, wait: bool = True,
+                    stream=None):
+    """Returns (out, offsets, n): image k's stream is out[offsets[k]:offsets[k+1]].
+    With wait=False the call does not synchronise and n is None."""
+    import torch
+    descs = (fe_image_desc * len(imgs))()
+    cap = 0
+    for k, im in enumerate(imgs):
+        H, W = im.shape
+        descs[k].data = _ptr(im)
+        descs[k].width, descs[k].height, descs[k].stride, descs[k].reserved = W, H, im.stride(0), 0
+        cap += fe_max_transforms(W, H, params.b_min)
+    dev = imgs[0].device
+    if out is None:
+        out = torch.empty((cap, 16), dtype=torch.uint8, device=dev)
+    if offsets is None:
+        offsets = torch.zeros(len(imgs) + 1, dtype=torch.int64, device=dev)
+    n = _SZ(0)
+    _check(load().fe_encode_batch(ctx, descs, len(imgs), ctypes.byref(params), _ptr(out), out.shape[0],
+                                  _ptr(offsets), ctypes.byref(n) if wait else None, _stream(stream)))
+    return out, offsets, (n.value if wait else None)
+
+
+def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: int, start=None, out=None,
+              stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.uint8, device=transforms.device)
+    n = int(transforms.shape[0])
+    _check(load().fe_decode(ctx, _ptr(transforms), n, width, height, b_max, iters, _ptr(start), _ptr(out),
+                            _stream(stream)))
+    return out
+
+
+def to_records(t) -> np.ndarray:
+    """Device (n, 16) uint8 tensor -> host structured array."""
+    a = t.detach().cpu().numpy()
+    return np.ascontiguousarray(a).view(TRANSFORM_DTYPE).reshape(-1)
+
+
+class Context:
+    """Owns one fe_ctx on a device; thin convenience over the C names."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = fe_create(device)
+
+    def close(self):
+        if self.handle:
+            fe_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def downsample(self, img, **kw):
+        return fe_downsample(self.handle, img, **kw)
+
+    def range_moments(self, img, block, xy, **kw):
+        return fe_range_moments(self.handle, img, block, xy, **kw)
+
+    def encode(self, img, b_max, b_min, thresholds, phase2=True, full_search=False, **kw):
+        return fe_encode(self.handle, img, make_params(b_max, b_min, thresholds, phase2, full_search), **kw)
+
+    def encode_batch(self, imgs, b_max, b_min, thresholds, phase2=True, **kw):
+        return fe_encode_batch(self.handle, imgs, make_params(b_max, b_min, thresholds, phase2), **kw)
+
+    def decode(self, transforms, width, height, b_max, iters, start=None, **kw):
+        return fe_decode(self.handle, transforms, width, height, b_max, iters, start=start, **kw)

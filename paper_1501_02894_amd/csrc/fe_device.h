@@ -1,0 +1,223 @@
+// Device helpers of the MNS encoder: packed-u8 moment accumulation from LDS,
+// team reductions over DPP, and the exact integer fits of phase 1 and phase 2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fe {
+
+template <int V>
+struct Log2 {
+  static constexpr int value = 1 + Log2<V / 2>::value;
+};
+template <>
+struct Log2<1> {
+  static constexpr int value = 0;
+};
+
+__device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc) {
+  return __builtin_amdgcn_udot4(a, b, acc, false);
+}
+
+// Sum over lanes of aligned power-of-two teams (T <= 16, within a DPP row).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_read(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int N>
+__device__ __forceinline__ void team_reduce(uint32_t (&a)[N], int T) {
+  if (T >= 2) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += dpp_read<0xB1>(a[j]);   // quad_perm 1,0,3,2
+  }
+  if (T >= 4) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += dpp_read<0x4E>(a[j]);   // quad_perm 2,3,0,1
+  }
+  if (T >= 8) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += dpp_read<0x141>(a[j]);  // row_half_mirror
+  }
+  if (T >= 16) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += dpp_read<0x140>(a[j]);  // row_mirror
+  }
+}
+
+// Q dwords of an LDS row starting at byte offset `off` of `arr`.
+template <int Q, bool ALIGNED>
+__device__ __forceinline__ void lds_row(const uint32_t* arr, int off, uint32_t (&o)[Q]) {
+  if constexpr (ALIGNED) {
+    const int w = off >> 2;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o[q] = arr[w + q];
+  } else {
+    const int w = off >> 2;
+    const uint32_t sh = (uint32_t)off & 3u;
+    uint32_t v[Q + 1];
+#pragma unroll
+    for (int q = 0; q <= Q; ++q) v[q] = arr[w + q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o[q] = __builtin_amdgcn_alignbyte(v[q + 1], v[q], sh);
+  }
+}
+
+// Moment slots: 0 Sum r, 1 Sum r^2, 2 Sum d, 3 Sum d^2, 4+e Sum r T_e(d).
+//
+// Adds the contribution of range rows i and B-1-i.  The range is B x B at
+// byte offset r_off of `img` (row pitch rp, dword aligned); the domain d is
+// the B x B window at byte offset d_off of `h0` (pitch hp); its transpose
+// is at byte offset t_off of `h0t` (pitch tp), i.e. dT[i][j] = d[j][i].
+//
+// With rrev the range with each row reversed, the eight isometries of the
+// table T_e(d)[i][j] = d[i][j], d[i][B-1-j], d[B-1-i][j], d[B-1-i][B-1-j],
+// d[j][i], d[B-1-j][i], d[j][B-1-i], d[B-1-j][B-1-i] give, per row i
+// (i' = B-1-i):  e0 r_i.d_i, e1 rrev_i.d_i, e2 r_i.d_i', e3 rrev_i.d_i',
+// e4 r_i.dT_i, e5 rrev_i.dT_i, e6 r_i.dT_i', e7 rrev_i.dT_i'.
+template <int B, bool ALIGNED>
+__device__ __forceinline__ void accumulate_row_pair(const uint32_t* img, int r_off, int rp,
+                                                    const uint32_t* h0, int d_off, int hp,
+                                                    const uint32_t* h0t, int t_off, int tp, int i,
+                                                    uint32_t (&a)[12]) {
+  constexpr int Q = B / 4;
+  const int ia = i, ib = B - 1 - i;
+  uint32_t ra[Q], rb[Q], da[Q], db[Q], ta[Q], tb[Q];
+  lds_row<Q, true>(img, r_off + ia * rp, ra);
+  lds_row<Q, true>(img, r_off + ib * rp, rb);
+  lds_row<Q, ALIGNED>(h0, d_off + ia * hp, da);
+  lds_row<Q, ALIGNED>(h0, d_off + ib * hp, db);
+  lds_row<Q, ALIGNED>(h0t, t_off + ia * tp, ta);
+  lds_row<Q, ALIGNED>(h0t, t_off + ib * tp, tb);
+  const uint32_t ones = 0x01010101u;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const uint32_t xa = ra[q], xb = rb[q];
+    const uint32_t ya = __builtin_bswap32(ra[Q - 1 - q]);   // rrev_i, dword q
+    const uint32_t yb = __builtin_bswap32(rb[Q - 1 - q]);
+    a[0] = dot4(xa, ones, dot4(xb, ones, a[0]));
+    a[1] = dot4(xa, xa, dot4(xb, xb, a[1]));
+    a[2] = dot4(da[q], ones, dot4(db[q], ones, a[2]));
+    a[3] = dot4(da[q], da[q], dot4(db[q], db[q], a[3]));
+    a[4] = dot4(xa, da[q], dot4(xb, db[q], a[4]));
+    a[5] = dot4(ya, da[q], dot4(yb, db[q], a[5]));
+    a[6] = dot4(xa, db[q], dot4(xb, da[q], a[6]));
+    a[7] = dot4(ya, db[q], dot4(yb, da[q], a[7]));
+    a[8] = dot4(xa, ta[q], dot4(xb, tb[q], a[8]));
+    a[9] = dot4(ya, ta[q], dot4(yb, tb[q], a[9]));
+    a[10] = dot4(xa, tb[q], dot4(xb, ta[q], a[10]));
+    a[11] = dot4(ya, tb[q], dot4(yb, ta[q], a[11]));
+  }
+}
+
+// Phase-1 fit packed as: bits 0-7 m, 8-10 k, 11-13 e, bit 14 accept.
+constexpr uint32_t kFitAccept = 1u << 14;
+constexpr uint32_t kFitDead = 1u << 15;   // set when the parent was stored by phase 2
+
+// Best (e, k/8) and luminance m of a B x B range from its moments, and
+// whether the scaled collage error S = 64 n E is below 64 n^2 t (or the
+// level is forced).  f(P) = min_k (k^2 Q - 16 k P) is non-increasing in P
+// and strictly decreasing where the minimising k is >= 1, so the best
+// isometry is the lowest e of maximal Sum r T_e(d) unless that P gives
+// k = 0, in which case every isometry scores 0 and e = 0.
+template <int B>
+__device__ __forceinline__ uint32_t fit_phase1(const uint32_t (&m)[12], bool forced, uint32_t t) {
+  constexpr int LOGN = 2 * Log2<B>::value;
+  constexpr int64_t N = (int64_t)B * B;
+  uint32_t best = m[4];
+  int e = 0;
+#pragma unroll
+  for (int j = 1; j < 8; ++j) {
+    if (m[4 + j] > best) {
+      best = m[4 + j];
+      e = j;
+    }
+  }
+  const int64_t sr = m[0], srr = m[1], sd = m[2], sdd = m[3];
+  const int64_t Q = ((int64_t)sdd << LOGN) - sd * sd;
+  const int64_t P = ((int64_t)best << LOGN) - sr * sd;
+  const int64_t P16 = P * 16;
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) k += ((int64_t)(2 * j + 1) * Q < P16) ? 1 : 0;
+  if (k == 0) e = 0;
+  const int64_t f = (int64_t)(k * k) * Q - (int64_t)(16 * k) * P;
+  const int64_t lum = (2 * sr + N) >> (LOGN + 1);
+  const int64_t R = ((int64_t)srr << LOGN) - sr * sr;
+  const int64_t dm = (lum << LOGN) - sr;
+  const int64_t S = f + 64 * R + 64 * dm * dm;
+  const bool acc = forced || S < (int64_t)(64 * N * N) * (int64_t)t;
+  return (uint32_t)lum | ((uint32_t)k << 8) | ((uint32_t)e << 11) | (acc ? kFitAccept : 0u);
+}
+
+// Phase-2 contrast sets (twentieths) and mean-difference bounds per level
+// 1..3: {.2,.5}, {.4,.65}, {.5,.9}; 5-bit (level 1) and 6-bit (levels 2, 3)
+// signed differences.
+__device__ __forceinline__ void phase2_consts(int level, int& c1, int& c2, int& delta) {
+  c1 = level == 1 ? 4 : (level == 2 ? 8 : 10);
+  c2 = level == 1 ? 10 : (level == 2 ? 13 : 18);
+  delta = level == 1 ? 15 : 31;
+}
+
+// Technique 1 for one parent whose four children (side b, Z order) have
+// identity moments mom[c] = {Sum r, Sum r^2, Sum d, Sum d^2, Sum r d}.
+// Returns accept; fills O_0..O_2 (O_3 by eq. (1)) and the contrast bits.
+template <int b>
+__device__ __forceinline__ bool fit_phase2(const uint32_t (&mom)[4][5], int m, int level, uint32_t t,
+                                           int (&O)[4], uint32_t& bits) {
+  constexpr int LOGNB = 2 * Log2<b>::value;
+  constexpr int64_t NB = (int64_t)b * b;
+  int c1, c2, delta;
+  phase2_consts(level, c1, c2, delta);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) O[c] = (int)((2 * (int64_t)mom[c][0] + NB) >> (LOGNB + 1));
+  O[3] = 4 * m - O[0] - O[1] - O[2];
+  bool ok = O[3] >= 0 && O[3] <= 255;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ok = ok && (O[c] - m <= delta) && (m - O[c] <= delta);
+  const int64_t thr = (int64_t)(400 * NB * NB) * (int64_t)t;
+  bits = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t sr = mom[c][0], srr = mom[c][1], sd = mom[c][2], sdd = mom[c][3], srd = mom[c][4];
+    const int64_t Q = (sdd << LOGNB) - sd * sd;
+    const int64_t P = (srd << LOGNB) - sr * sd;
+    const int64_t R = (srr << LOGNB) - sr * sr;
+    const int64_t f1 = (int64_t)(c1 * c1) * Q - (int64_t)(40 * c1) * P;
+    const int64_t f2 = (int64_t)(c2 * c2) * Q - (int64_t)(40 * c2) * P;
+    const bool use2 = f2 < f1;
+    const int64_t dm = ((int64_t)O[c] << LOGNB) - sr;
+    const int64_t S = (use2 ? f2 : f1) + 400 * R + 400 * dm * dm;
+    ok = ok && S < thr;
+    bits |= (use2 ? 1u : 0u) << c;
+  }
+  return ok;
+}
+
+// Record words (little-endian fe_transform).
+__device__ __forceinline__ uint4 make_record(int x, int y, int dx, int dy, int level, int flags,
+                                             int iso, int s_idx, int lum, int d0, int d1, int d2) {
+  uint4 w;
+  w.x = (uint32_t)x | ((uint32_t)y << 16);
+  w.y = (uint32_t)dx | ((uint32_t)dy << 16);
+  w.z = (uint32_t)level | ((uint32_t)flags << 8) | ((uint32_t)iso << 16) | ((uint32_t)s_idx << 24);
+  w.w = (uint32_t)lum | (((uint32_t)d0 & 0xffu) << 8) | (((uint32_t)d1 & 0xffu) << 16) |
+        (((uint32_t)d2 & 0xffu) << 24);
+  return w;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Four round-half-up 2x2 means of an 8-wide, 2-row pixel group:
+// a0/a1 = row 0 pixels 0-3 / 4-7, b0/b1 = row 1.
+__device__ __forceinline__ uint32_t mean2x2_x4(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
+  const uint32_t M = 0x00FF00FFu;
+  uint32_t s0 = (a0 & M) + ((a0 >> 8) & M) + (b0 & M) + ((b0 >> 8) & M) + 0x00020002u;
+  uint32_t s1 = (a1 & M) + ((a1 >> 8) & M) + (b1 & M) + ((b1 >> 8) & M) + 0x00020002u;
+  s0 = (s0 >> 2) & M;
+  s1 = (s1 >> 2) & M;
+  return __builtin_amdgcn_perm(s1, s0, 0x06040200u);
+}
+
+}  // namespace fe

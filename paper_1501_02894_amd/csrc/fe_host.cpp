@@ -1,0 +1,305 @@
+// Host driver of the C ABI: contexts, scratch management and the launch
+// sequences of encode / batch encode / decode / the stand-alone steps.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/fe.h"
+#include "fe_common.h"
+#include "fe_internal.h"
+
+struct fe_ctx {
+  int device = 0;
+  hipEvent_t table_ready = nullptr;   // last copy out of h_table finished
+  fe::ImgDev* h_table = nullptr;      // pinned staging of the image table
+  size_t h_table_n = 0;
+  uint64_t* h_scalars = nullptr;      // pinned read-back words
+  fe::ImgDev* d_table = nullptr;
+  size_t d_table_n = 0;
+  uint4* staging = nullptr;
+  size_t staging_n = 0;
+  uint64_t* masks = nullptr;
+  size_t masks_n = 0;
+  uint32_t* chunk_sum = nullptr;
+  size_t chunk_n = 0;
+  uint64_t* offsets = nullptr;
+  size_t offsets_n = 0;
+  uint32_t* flags = nullptr;          // small device counters
+  uint8_t* tmp_img = nullptr;
+  size_t tmp_n = 0;
+  fe::TileShape shape_override[33][5] = {};
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+fe_status hip_fail(hipError_t e, const char* what) {
+  return fe::fail(e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FE_HIP(call, what)                      \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Grow a device buffer to hold n elements (contents not kept).
+template <typename T>
+fe_status ensure(T*& p, size_t& cap, size_t n, const char* what) {
+  if (n <= cap && p) return FE_OK;
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  size_t want = std::max<size_t>(n, 1);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), want * sizeof(T));
+  if (e != hipSuccess) {
+    p = nullptr;
+    return hip_fail(e, what);
+  }
+  cap = want;
+  return FE_OK;
+}
+
+fe::TileShape pick_shape(fe_ctx* ctx, int b_max, int L) {
+  fe::TileShape o = ctx->shape_override[b_max][L];
+  if (o.gx > 0) return o;
+  fe::TileShape shapes[8];
+  const int k = fe::encode_shapes(b_max, L, shapes, 8);
+  return k > 0 ? shapes[0] : fe::TileShape{0, 0};
+}
+
+// Copy `n` table entries to the device through the pinned staging buffer.
+fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, hipStream_t s) {
+  FE_HIP(hipEventSynchronize(ctx->table_ready), "wait for previous table copy");
+  if (n > ctx->h_table_n) {
+    if (ctx->h_table) (void)hipHostFree(ctx->h_table);
+    ctx->h_table = nullptr;
+    ctx->h_table_n = 0;
+    FE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_table), n * sizeof(fe::ImgDev), hipHostMallocDefault),
+           "pinned image table");
+    ctx->h_table_n = n;
+  }
+  fe_status st = ensure(ctx->d_table, ctx->d_table_n, n, "device image table");
+  if (st != FE_OK) return st;
+  memcpy(ctx->h_table, src, n * sizeof(fe::ImgDev));
+  FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, n * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
+         "image table copy");
+  FE_HIP(hipEventRecord(ctx->table_ready, s), "table event");
+  return FE_OK;
+}
+
+// Shared MNS encode of a list of images with common parameters.
+fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
+                        fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  const int bmax = (int)p->b_max;
+  const fe::TileShape shape = pick_shape(ctx, bmax, L);
+  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
+  const int cells = 1 << (2 * (L - 1));
+  std::vector<fe::ImgDev> table(n_imgs);
+  uint64_t tiles = 0;
+  uint32_t wgs = 0;
+  for (uint32_t k = 0; k < n_imgs; ++k) {
+    fe::ImgDev& d = table[k];
+    d.data = imgs[k].data;
+    d.width = imgs[k].width;
+    d.height = imgs[k].height;
+    d.stride = imgs[k].stride;
+    d.tiles_x = d.width / p->b_max;
+    d.tiles_y = d.height / p->b_max;
+    d.groups_x = (d.tiles_x + shape.gx - 1) / shape.gx;
+    d.groups_y = (d.tiles_y + shape.gy - 1) / shape.gy;
+    d.wg_first = wgs;
+    d.pad = 0;
+    d.tile_first = tiles;
+    const uint64_t g = (uint64_t)d.groups_x * d.groups_y;
+    if (wgs + g > 0x7fffffffull) return fe::fail(FE_ERR_SHAPE, "batch too large (workgroups)");
+    wgs += (uint32_t)g;
+    tiles += (uint64_t)d.tiles_x * d.tiles_y;
+  }
+  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  fe_status st;
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
+  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
+  uint64_t* offsets = d_offsets;
+  if (!offsets) {
+    if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
+    offsets = ctx->offsets;
+  }
+  if ((st = upload_table(ctx, table.data(), n_imgs, s)) != FE_OK) return st;
+
+  FE_HIP(fe::launch_zero_u32(ctx->chunk_sum, chunks, s), "zero chunk sums");
+  fe::EncodeArgs a{};
+  a.imgs = ctx->d_table;
+  a.n_imgs = n_imgs;
+  a.n_wg = wgs;
+  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
+  a.staging = ctx->staging;
+  a.masks = ctx->masks;
+  a.chunk_sum = ctx->chunk_sum;
+  FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
+  FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->staging,
+                            reinterpret_cast<uint4*>(d_out), (uint64_t)cap, offsets, s),
+         "scatter kernel launch");
+  if (n_out) {
+    FE_HIP(hipMemcpyAsync(ctx->h_scalars, offsets + n_imgs, sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+           "count read-back");
+    FE_HIP(hipStreamSynchronize(s), "encode");
+    *n_out = (size_t)ctx->h_scalars[0];
+    if (*n_out > cap)
+      return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
+  }
+  return FE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_create(int device, fe_ctx** out) {
+  fe::clear_error();
+  if (!out) return fe::fail(FE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return fe::fail(FE_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= count) return fe::fail(FE_ERR_DEVICE, "device %d out of range (%d)", device, count);
+  hipDeviceProp_t prop;
+  FE_HIP(hipGetDeviceProperties(&prop, device), "device properties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fe::fail(FE_ERR_DEVICE, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+  DeviceGuard g(device);
+  fe_ctx* c = new fe_ctx();
+  c->device = device;
+  hipError_t e1 = hipEventCreateWithFlags(&c->table_ready, hipEventDisableTiming);
+  hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&c->h_scalars), 64, hipHostMallocDefault);
+  hipError_t e3 = hipMalloc(reinterpret_cast<void**>(&c->flags), 64);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    fe_destroy(c);
+    return fe::fail(FE_ERR_OOM, "context allocation failed");
+  }
+  *out = c;
+  return FE_OK;
+}
+
+void fe_destroy(fe_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->table_ready) (void)hipEventDestroy(c->table_ready);
+  if (c->h_table) (void)hipHostFree(c->h_table);
+  if (c->h_scalars) (void)hipHostFree(c->h_scalars);
+  (void)hipFree(c->d_table);
+  (void)hipFree(c->staging);
+  (void)hipFree(c->masks);
+  (void)hipFree(c->chunk_sum);
+  (void)hipFree(c->offsets);
+  (void)hipFree(c->flags);
+  (void)hipFree(c->tmp_img);
+  delete c;
+}
+
+fe_status fe_downsample(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride,
+                        uint8_t* d_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_img || !d_out) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (w < 2 || h < 2 || (w & 1) || (h & 1)) return fe::fail(FE_ERR_SHAPE, "sides must be even and >= 2");
+  if (stride < w || stride % 4 || ((uintptr_t)d_img & 3))
+    return fe::fail(FE_ERR_SHAPE, "stride must be >= width, a multiple of 4, and the image 4-byte aligned");
+  DeviceGuard g(ctx->device);
+  FE_HIP(fe::launch_downsample(d_img, w, h, stride, d_out, (hipStream_t)stream), "downsample launch");
+  return FE_OK;
+}
+
+fe_status fe_range_moments(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride,
+                           uint32_t block, const uint32_t* d_xy, uint32_t count, uint32_t* d_moments,
+                           void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_img || (count && (!d_xy || !d_moments))) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (block != 4 && block != 8 && block != 16 && block != 32)
+    return fe::fail(FE_ERR_INVALID, "block must be 4, 8, 16 or 32");
+  fe_status st = fe::check_shape(w, h, stride, block);
+  if (st != FE_OK) return st;
+  DeviceGuard g(ctx->device);
+  FE_HIP(fe::launch_range_moments(d_img, w, h, stride, (int)block, d_xy, count, d_moments, (hipStream_t)stream),
+         "moments launch");
+  return FE_OK;
+}
+
+fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride,
+                    const fe_params* p, fe_transform* d_out, size_t cap, size_t* n_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_img || !d_out || !n_out) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st = fe_validate(w, h, stride, p);
+  if (st != FE_OK) return st;
+  if ((uintptr_t)d_img & 3) return fe::fail(FE_ERR_SHAPE, "image must be 4-byte aligned");
+  if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
+  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "exhaustive search is not available");
+  DeviceGuard g(ctx->device);
+  fe_image_desc one{d_img, w, h, stride, 0};
+  return encode_images(ctx, &one, 1, p, d_out, cap, nullptr, n_out, (hipStream_t)stream);
+}
+
+fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p,
+                          fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !h_imgs || !d_out || !d_offsets || n_imgs == 0) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st = fe::check_params(p);
+  if (st != FE_OK) return st;
+  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
+  if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
+  for (uint32_t k = 0; k < n_imgs; ++k) {
+    if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
+    if ((st = fe::check_shape(h_imgs[k].width, h_imgs[k].height, h_imgs[k].stride, p->b_max)) != FE_OK) return st;
+    if ((uintptr_t)h_imgs[k].data & 3) return fe::fail(FE_ERR_SHAPE, "image %u must be 4-byte aligned", k);
+  }
+  DeviceGuard g(ctx->device);
+  return encode_images(ctx, h_imgs, n_imgs, p, d_out, cap, d_offsets, n_out, (hipStream_t)stream);
+}
+
+fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
+                    uint32_t iters, const uint8_t* d_start, uint8_t* d_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_out || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (!fe::is_pow2(b_max) || b_max < 4 || b_max > 32) return fe::fail(FE_ERR_INVALID, "bad b_max %u", b_max);
+  if (w < 2 || h < 2 || w > 65536 || h > 65536) return fe::fail(FE_ERR_SHAPE, "bad image size %ux%u", w, h);
+  if ((uintptr_t)d_t & 15) return fe::fail(FE_ERR_INVALID, "transforms must be 16-byte aligned");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  fe::DecodeArgs a{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
+  FE_HIP(fe::launch_zero_u32(ctx->flags, 1, s), "zero flag");
+  FE_HIP(fe::launch_decode_check(a, ctx->flags, s), "check launch");
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "flag read-back");
+  FE_HIP(hipStreamSynchronize(s), "transform check");
+  const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
+  if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms are out of range for a %ux%u image", bad, w, h);
+  fe_status st = ensure(ctx->tmp_img, ctx->tmp_n, (size_t)w * h, "decode buffer");
+  if (st != FE_OK) return st;
+  uint8_t* buf[2] = {d_out, ctx->tmp_img};
+  const int s0 = (int)(iters & 1u);   // iterate t lives in buf[s0 ^ (t & 1)]; t = iters in d_out
+  FE_HIP(fe::launch_decode_fill(buf[1 - s0], d_start, w, h, s), "fill");
+  FE_HIP(fe::launch_decode_fill(buf[s0], d_start, w, h, s), "fill");
+  for (uint32_t t = 0; t < iters; ++t) {
+    FE_HIP(fe::launch_decode_iter(a, buf[s0 ^ (int)(t & 1u)], buf[s0 ^ (int)((t + 1) & 1u)], s), "decode launch");
+  }
+  return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fe {
+
+// One image as the device sees it (batch table entry).
+struct ImgDev {
+  const uint8_t* data;
+  uint32_t width, height, stride;
+  uint32_t tiles_x, tiles_y;    // top-level tiles per row / column
+  uint32_t groups_x, groups_y;  // workgroup super-tiles per row / column
+  uint32_t wg_first;            // first logical workgroup of this image
+  uint32_t pad;
+  uint64_t tile_first;          // global index of this image's first tile
+};
+
+// Per-call encoder constants (passed by value).
+struct EncodeArgs {
+  const ImgDev* imgs;
+  uint32_t n_imgs;
+  uint32_t n_wg;       // logical workgroups over all images
+  uint32_t phase2;     // run Technique 1
+  uint32_t pad;
+  uint32_t thr[4];     // MSE thresholds of levels 1..L-1
+  uint4* staging;      // tile-major record slots: tile * cells + morton cell
+  uint64_t* masks;     // per tile: bit c set when cell c holds a record
+  uint32_t* chunk_sum; // per CHUNK tiles: number of records
+};
+
+constexpr int kChunkTiles = 1024;  // tiles per scatter workgroup
+
+// Tile shape of the encode kernel: GX x GY top tiles per workgroup.
+struct TileShape {
+  int gx, gy;
+};
+
+// Supported tile shapes for (b_max, levels); the first is the default.
+int encode_shapes(int b_max, int levels, TileShape* out, int max_out);
+
+// Launch the fused encode kernel for (b_max, levels, shape).  Returns
+// hipErrorInvalidValue when the combination is not instantiated.
+hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const EncodeArgs& args,
+                            hipStream_t stream);
+
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
+
+// Exclusive scan of per-tile record counts and copy of the records from
+// staging into stream order; writes per-image offsets and the total
+// (offsets[n_imgs]).
+hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, uint64_t total_tiles, int cells,
+                          const uint64_t* masks, const uint32_t* chunk_sum, const uint4* staging,
+                          uint4* out, uint64_t cap, uint64_t* offsets, hipStream_t stream);
+
+hipError_t launch_downsample(const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                             uint8_t* out, hipStream_t stream);
+
+hipError_t launch_range_moments(const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                                int block, const uint32_t* xy, uint32_t count, uint32_t* mom,
+                                hipStream_t stream);
+
+// Decoder.
+struct DecodeArgs {
+  const uint4* recs;
+  uint64_t n;
+  uint32_t width, height, b_max, pad;
+};
+hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t stream);
+hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint32_t h,
+                              hipStream_t stream);
+hipError_t launch_decode_iter(const DecodeArgs& a, const uint8_t* cur, uint8_t* nxt,
+                              hipStream_t stream);
+
+}  // namespace fe
