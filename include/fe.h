@@ -245,6 +245,24 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
                     uint32_t height, uint32_t b_max, uint32_t iters, const uint8_t* d_start,
                     uint8_t* d_out, void* stream);
 
+/*
+ * Kernel timing.  While enabled, each launch of the library's main kernels
+ * (below) is bracketed by HIP events recorded on the launch's own stream.
+ * fe_timing_read waits for those events, adds each kernel's event-to-event
+ * time (milliseconds) and launch count into ms[k] / launches[k] for
+ * k < n (n <= FE_TIMING_SLOTS), and clears them.  At most 4096 launches are
+ * held between reads; later ones are not timed.  Enabling timing adds an
+ * event record before and after each timed launch and nothing else.
+ */
+#define FE_TIMING_ENCODE 0      /* fused MNS quadtree kernel */
+#define FE_TIMING_SCATTER 1     /* stream-order kernel */
+#define FE_TIMING_DECODE 2      /* one decoder iteration */
+#define FE_TIMING_FULLSEARCH 3  /* exhaustive-search GEMM + argmin */
+#define FE_TIMING_SLOTS 8
+
+fe_status fe_timing_enable(fe_ctx* ctx, int enable);
+fe_status fe_timing_read(fe_ctx* ctx, double* ms, uint64_t* launches, uint32_t n);
+
 #ifdef __cplusplus
 }
 #endif

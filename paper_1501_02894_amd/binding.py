@@ -71,7 +71,13 @@ _SIGNATURES = {
     "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
+    "fe_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "fe_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
+                                      _U32]),
 }
+
+FE_TIMING_ENCODE, FE_TIMING_SCATTER, FE_TIMING_DECODE, FE_TIMING_FULLSEARCH = 0, 1, 2, 3
+FE_TIMING_SLOTS = 8
 
 
 def load(path: str = LIB_PATH):
@@ -217,6 +223,18 @@ def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: 
     _check(load().fe_decode(ctx, _ptr(transforms), n, width, height, b_max, iters, _ptr(start), _ptr(out),
                             _stream(stream)))
     return out
+
+
+def fe_timing_enable(ctx: int, enable: bool = True) -> None:
+    _check(load().fe_timing_enable(ctx, 1 if enable else 0))
+
+
+def fe_timing_read(ctx: int):
+    """Returns (ms[8], launches[8]) per timed kernel slot, then clears."""
+    ms = (ctypes.c_double * FE_TIMING_SLOTS)()
+    cnt = (ctypes.c_uint64 * FE_TIMING_SLOTS)()
+    _check(load().fe_timing_read(ctx, ms, cnt, FE_TIMING_SLOTS))
+    return list(ms), list(cnt)
 
 
 def to_records(t) -> np.ndarray:

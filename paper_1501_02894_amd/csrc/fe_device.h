@@ -121,10 +121,15 @@ constexpr uint32_t kFitDead = 1u << 15;   // set when the parent was stored by p
 // and strictly decreasing where the minimising k is >= 1, so the best
 // isometry is the lowest e of maximal Sum r T_e(d) unless that P gives
 // k = 0, in which case every isometry scores 0 and e = 0.
+//
+// The arithmetic is float64 but exact: every operand and every partial
+// result is an integer of magnitude below 2^53 (n <= 1024, sums of 8-bit
+// pixels: products below 2^37, k^2 Q and 16 k P below 2^44); the threshold
+// 64 n^2 t is t times a power of two, hence exact too.
 template <int B>
 __device__ __forceinline__ uint32_t fit_phase1(const uint32_t (&m)[12], bool forced, uint32_t t) {
   constexpr int LOGN = 2 * Log2<B>::value;
-  constexpr int64_t N = (int64_t)B * B;
+  constexpr double N = (double)(B * B);
   uint32_t best = m[4];
   int e = 0;
 #pragma unroll
@@ -134,21 +139,22 @@ __device__ __forceinline__ uint32_t fit_phase1(const uint32_t (&m)[12], bool for
       e = j;
     }
   }
-  const int64_t sr = m[0], srr = m[1], sd = m[2], sdd = m[3];
-  const int64_t Q = ((int64_t)sdd << LOGN) - sd * sd;
-  const int64_t P = ((int64_t)best << LOGN) - sr * sd;
-  const int64_t P16 = P * 16;
+  const double sr = (double)m[0], srr = (double)m[1], sd = (double)m[2], sdd = (double)m[3];
+  const double Q = N * sdd - sd * sd;
+  const double P = N * (double)best - sr * sd;
+  const double P16 = 16.0 * P;
   int k = 0;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) k += ((int64_t)(2 * j + 1) * Q < P16) ? 1 : 0;
+  for (int j = 0; j < 7; ++j) k += ((double)(2 * j + 1) * Q < P16) ? 1 : 0;
   if (k == 0) e = 0;
-  const int64_t f = (int64_t)(k * k) * Q - (int64_t)(16 * k) * P;
-  const int64_t lum = (2 * sr + N) >> (LOGN + 1);
-  const int64_t R = ((int64_t)srr << LOGN) - sr * sr;
-  const int64_t dm = (lum << LOGN) - sr;
-  const int64_t S = f + 64 * R + 64 * dm * dm;
-  const bool acc = forced || S < (int64_t)(64 * N * N) * (int64_t)t;
-  return (uint32_t)lum | ((uint32_t)k << 8) | ((uint32_t)e << 11) | (acc ? kFitAccept : 0u);
+  const double kd = (double)k;
+  const double f = (kd * kd) * Q - (16.0 * kd) * P;
+  const uint32_t lum = (2u * m[0] + (uint32_t)(B * B)) >> (LOGN + 1);
+  const double R = N * srr - sr * sr;
+  const double dm = (double)lum * N - sr;
+  const double S = f + 64.0 * R + 64.0 * (dm * dm);
+  const bool acc = forced || S < (64.0 * N * N) * (double)t;
+  return lum | ((uint32_t)k << 8) | ((uint32_t)e << 11) | (acc ? kFitAccept : 0u);
 }
 
 // Phase-2 contrast sets (twentieths) and mean-difference bounds per level
@@ -163,32 +169,38 @@ __device__ __forceinline__ void phase2_consts(int level, int& c1, int& c2, int& 
 // Technique 1 for one parent whose four children (side b, Z order) have
 // identity moments mom[c] = {Sum r, Sum r^2, Sum d, Sum d^2, Sum r d}.
 // Returns accept; fills O_0..O_2 (O_3 by eq. (1)) and the contrast bits.
+// float64, exact as in fit_phase1 (c <= 18, n_b <= 256: every partial
+// result below 2^44; a threshold above 2^53 exceeds every S, so its
+// rounding cannot change the comparison).
 template <int b>
 __device__ __forceinline__ bool fit_phase2(const uint32_t (&mom)[4][5], int m, int level, uint32_t t,
                                            int (&O)[4], uint32_t& bits) {
   constexpr int LOGNB = 2 * Log2<b>::value;
-  constexpr int64_t NB = (int64_t)b * b;
+  constexpr double NB = (double)(b * b);
   int c1, c2, delta;
   phase2_consts(level, c1, c2, delta);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) O[c] = (int)((2 * (int64_t)mom[c][0] + NB) >> (LOGNB + 1));
+  for (int c = 0; c < 3; ++c) O[c] = (int)((2u * mom[c][0] + (uint32_t)(b * b)) >> (LOGNB + 1));
   O[3] = 4 * m - O[0] - O[1] - O[2];
   bool ok = O[3] >= 0 && O[3] <= 255;
 #pragma unroll
   for (int c = 0; c < 4; ++c) ok = ok && (O[c] - m <= delta) && (m - O[c] <= delta);
-  const int64_t thr = (int64_t)(400 * NB * NB) * (int64_t)t;
+  const double thr = (400.0 * NB * NB) * (double)t;
+  const double a1 = (double)(c1 * c1), b1 = (double)(40 * c1);
+  const double a2 = (double)(c2 * c2), b2 = (double)(40 * c2);
   bits = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int64_t sr = mom[c][0], srr = mom[c][1], sd = mom[c][2], sdd = mom[c][3], srd = mom[c][4];
-    const int64_t Q = (sdd << LOGNB) - sd * sd;
-    const int64_t P = (srd << LOGNB) - sr * sd;
-    const int64_t R = (srr << LOGNB) - sr * sr;
-    const int64_t f1 = (int64_t)(c1 * c1) * Q - (int64_t)(40 * c1) * P;
-    const int64_t f2 = (int64_t)(c2 * c2) * Q - (int64_t)(40 * c2) * P;
+    const double sr = (double)mom[c][0], srr = (double)mom[c][1], sd = (double)mom[c][2];
+    const double sdd = (double)mom[c][3], srd = (double)mom[c][4];
+    const double Q = NB * sdd - sd * sd;
+    const double P = NB * srd - sr * sd;
+    const double R = NB * srr - sr * sr;
+    const double f1 = a1 * Q - b1 * P;
+    const double f2 = a2 * Q - b2 * P;
     const bool use2 = f2 < f1;
-    const int64_t dm = ((int64_t)O[c] << LOGNB) - sr;
-    const int64_t S = (use2 ? f2 : f1) + 400 * R + 400 * dm * dm;
+    const double dm = (double)O[c] * NB - sr;
+    const double S = (use2 ? f2 : f1) + 400.0 * R + 400.0 * (dm * dm);
     ok = ok && S < thr;
     bits |= (use2 ? 1u : 0u) << c;
   }

@@ -24,12 +24,20 @@ struct fe_ctx {
   size_t masks_n = 0;
   uint32_t* chunk_sum = nullptr;
   size_t chunk_n = 0;
+  uint64_t* chunk_base = nullptr;
+  size_t chunk_base_n = 0;
   uint64_t* offsets = nullptr;
   size_t offsets_n = 0;
   uint32_t* flags = nullptr;          // small device counters
   uint8_t* tmp_img = nullptr;
   size_t tmp_n = 0;
   fe::TileShape shape_override[33][5] = {};
+  // kernel timing (fe_timing_enable)
+  bool timing = false;
+  static constexpr int kTimingCap = 4096;
+  hipEvent_t* ev = nullptr;           // 2 * kTimingCap events
+  int ev_slot[kTimingCap] = {};
+  int ev_used = 0;
 };
 
 namespace {
@@ -75,6 +83,22 @@ fe_status ensure(T*& p, size_t& cap, size_t n, const char* what) {
   return FE_OK;
 }
 
+// Bracket a launch with timing events when timing is on.
+struct Timed {
+  fe_ctx* c;
+  hipStream_t s;
+  int idx = -1;
+  Timed(fe_ctx* ctx, int slot, hipStream_t stream) : c(ctx), s(stream) {
+    if (!c->timing || !c->ev || c->ev_used >= fe_ctx::kTimingCap) return;
+    idx = c->ev_used++;
+    c->ev_slot[idx] = slot;
+    (void)hipEventRecord(c->ev[2 * idx], s);
+  }
+  ~Timed() {
+    if (idx >= 0) (void)hipEventRecord(c->ev[2 * idx + 1], s);
+  }
+};
+
 fe::TileShape pick_shape(fe_ctx* ctx, int b_max, int L) {
   fe::TileShape o = ctx->shape_override[b_max][L];
   if (o.gx > 0) return o;
@@ -83,21 +107,26 @@ fe::TileShape pick_shape(fe_ctx* ctx, int b_max, int L) {
   return k > 0 ? shapes[0] : fe::TileShape{0, 0};
 }
 
-// Copy `n` table entries to the device through the pinned staging buffer.
+// Copy `n` table entries, followed by their wg_first values, to the device
+// through the pinned staging buffer (one copy).  Table slots hold
+// fe::ImgDev; the wg_first words start at slot n.
 fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, hipStream_t s) {
+  const size_t slots = n + (n * sizeof(uint32_t) + sizeof(fe::ImgDev) - 1) / sizeof(fe::ImgDev);
   FE_HIP(hipEventSynchronize(ctx->table_ready), "wait for previous table copy");
-  if (n > ctx->h_table_n) {
+  if (slots > ctx->h_table_n) {
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
     ctx->h_table = nullptr;
     ctx->h_table_n = 0;
-    FE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_table), n * sizeof(fe::ImgDev), hipHostMallocDefault),
+    FE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_table), slots * sizeof(fe::ImgDev), hipHostMallocDefault),
            "pinned image table");
-    ctx->h_table_n = n;
+    ctx->h_table_n = slots;
   }
-  fe_status st = ensure(ctx->d_table, ctx->d_table_n, n, "device image table");
+  fe_status st = ensure(ctx->d_table, ctx->d_table_n, slots, "device image table");
   if (st != FE_OK) return st;
   memcpy(ctx->h_table, src, n * sizeof(fe::ImgDev));
-  FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, n * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
+  uint32_t* wf = reinterpret_cast<uint32_t*>(ctx->h_table + n);
+  for (size_t k = 0; k < n; ++k) wf[k] = src[k].wg_first;
+  FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
          "image table copy");
   FE_HIP(hipEventRecord(ctx->table_ready, s), "table event");
   return FE_OK;
@@ -137,6 +166,7 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
   uint64_t* offsets = d_offsets;
   if (!offsets) {
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
@@ -144,20 +174,25 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   }
   if ((st = upload_table(ctx, table.data(), n_imgs, s)) != FE_OK) return st;
 
-  FE_HIP(fe::launch_zero_u32(ctx->chunk_sum, chunks, s), "zero chunk sums");
   fe::EncodeArgs a{};
   a.imgs = ctx->d_table;
+  a.wg_first = reinterpret_cast<const uint32_t*>(ctx->d_table + n_imgs);
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
   a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
   for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
   a.staging = ctx->staging;
   a.masks = ctx->masks;
-  a.chunk_sum = ctx->chunk_sum;
-  FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
-  FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->staging,
-                            reinterpret_cast<uint4*>(d_out), (uint64_t)cap, offsets, s),
-         "scatter kernel launch");
+  {
+    Timed t(ctx, FE_TIMING_ENCODE, s);
+    FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
+  }
+  {
+    Timed t(ctx, FE_TIMING_SCATTER, s);
+    FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->chunk_base,
+                              ctx->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, offsets, s),
+           "scatter kernel launch");
+  }
   if (n_out) {
     FE_HIP(hipMemcpyAsync(ctx->h_scalars, offsets + n_imgs, sizeof(uint64_t), hipMemcpyDeviceToHost, s),
            "count read-back");
@@ -210,9 +245,15 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->staging);
   (void)hipFree(c->masks);
   (void)hipFree(c->chunk_sum);
+  (void)hipFree(c->chunk_base);
   (void)hipFree(c->offsets);
   (void)hipFree(c->flags);
   (void)hipFree(c->tmp_img);
+  if (c->ev) {
+    for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
+      if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete[] c->ev;
+  }
   delete c;
 }
 
@@ -297,8 +338,44 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
   FE_HIP(fe::launch_decode_fill(buf[1 - s0], d_start, w, h, s), "fill");
   FE_HIP(fe::launch_decode_fill(buf[s0], d_start, w, h, s), "fill");
   for (uint32_t t = 0; t < iters; ++t) {
+    Timed tm(ctx, FE_TIMING_DECODE, s);
     FE_HIP(fe::launch_decode_iter(a, buf[s0 ^ (int)(t & 1u)], buf[s0 ^ (int)((t + 1) & 1u)], s), "decode launch");
   }
+  return FE_OK;
+}
+
+fe_status fe_timing_enable(fe_ctx* ctx, int enable) {
+  fe::clear_error();
+  if (!ctx) return fe::fail(FE_ERR_INVALID, "NULL context");
+  DeviceGuard g(ctx->device);
+  if (enable && !ctx->ev) {
+    ctx->ev = new hipEvent_t[2 * fe_ctx::kTimingCap]();
+    for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
+      FE_HIP(hipEventCreate(&ctx->ev[i]), "timing events");
+  }
+  ctx->timing = enable != 0;
+  return FE_OK;
+}
+
+fe_status fe_timing_read(fe_ctx* ctx, double* ms, uint64_t* launches, uint32_t n) {
+  fe::clear_error();
+  if (!ctx || (n && (!ms || !launches)) || n > FE_TIMING_SLOTS) return fe::fail(FE_ERR_INVALID, "bad arguments");
+  DeviceGuard g(ctx->device);
+  for (uint32_t k = 0; k < n; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (int i = 0; i < ctx->ev_used; ++i) {
+    FE_HIP(hipEventSynchronize(ctx->ev[2 * i + 1]), "timing event");
+    float t = 0.f;
+    FE_HIP(hipEventElapsedTime(&t, ctx->ev[2 * i], ctx->ev[2 * i + 1]), "timing elapsed");
+    const int slot = ctx->ev_slot[i];
+    if (slot >= 0 && (uint32_t)slot < n) {
+      ms[slot] += t;
+      launches[slot] += 1;
+    }
+  }
+  ctx->ev_used = 0;
   return FE_OK;
 }
 

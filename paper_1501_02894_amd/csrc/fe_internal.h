@@ -21,6 +21,7 @@ struct ImgDev {
 // Per-call encoder constants (passed by value).
 struct EncodeArgs {
   const ImgDev* imgs;
+  const uint32_t* wg_first;  // per image: first logical workgroup (sorted)
   uint32_t n_imgs;
   uint32_t n_wg;       // logical workgroups over all images
   uint32_t phase2;     // run Technique 1
@@ -28,10 +29,9 @@ struct EncodeArgs {
   uint32_t thr[4];     // MSE thresholds of levels 1..L-1
   uint4* staging;      // tile-major record slots: tile * cells + morton cell
   uint64_t* masks;     // per tile: bit c set when cell c holds a record
-  uint32_t* chunk_sum; // per CHUNK tiles: number of records
 };
 
-constexpr int kChunkTiles = 1024;  // tiles per scatter workgroup
+constexpr int kChunkTiles = 256;  // tiles per scatter workgroup
 
 // Tile shape of the encode kernel: GX x GY top tiles per workgroup.
 struct TileShape {
@@ -48,12 +48,14 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
 
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
 
-// Exclusive scan of per-tile record counts and copy of the records from
-// staging into stream order; writes per-image offsets and the total
-// (offsets[n_imgs]).
+// Count records per chunk of tiles, scan the chunk counts, and copy the
+// records from staging into stream order; writes per-image offsets and the
+// total (offsets[n_imgs]).  chunk_sum needs ceil(tiles / kChunkTiles)
+// entries, chunk_base one more.
 hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, uint64_t total_tiles, int cells,
-                          const uint64_t* masks, const uint32_t* chunk_sum, const uint4* staging,
-                          uint4* out, uint64_t cap, uint64_t* offsets, hipStream_t stream);
+                          const uint64_t* masks, uint32_t* chunk_sum, uint64_t* chunk_base,
+                          const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
+                          hipStream_t stream);
 
 hipError_t launch_downsample(const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
                              uint8_t* out, hipStream_t stream);

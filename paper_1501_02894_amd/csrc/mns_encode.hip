@@ -35,24 +35,28 @@ namespace {
 template <int BMAX, int L, int GX, int GY>
 struct Geo {
   static constexpr int BMIN = BMAX >> (L - 1);
-  static constexpr int NT = GX * GY;
+  static constexpr int NT = GX * GY;                          // tiles per workgroup
+  static constexpr int NTW = NT / 4;                          // tiles per wave
   static constexpr int CELLS = 1 << (2 * (L - 1));
-  static constexpr int CAP = NT * CELLS;                      // deepest list bound
-  static constexpr int PCAP = CAP / 4 > 0 ? CAP / 4 : 1;      // parent list bound
+  static constexpr int CAPW = NTW * CELLS;                    // per-wave deepest list bound
+  static constexpr int PCAPW = CAPW / 4 > 0 ? CAPW / 4 : 1;   // per-wave parent list bound
+  static constexpr int TW = GX * BMAX, TH = GY * BMAX;        // tile block in pixels
+  static constexpr int TPITCH = TW + 4;                       // tile pixel row pitch (bytes)
   static constexpr int RWA = ((GX + 1) * BMAX + 6 + 7) & ~7;  // region width bound (px)
   static constexpr int RHA = (GY + 1) * BMAX + 8;             // region height bound (px)
-  static constexpr int RP = RWA + 4;                          // image row pitch (bytes)
   static constexpr int HW = RWA / 2, HH = RHA / 2;            // H0 region bounds
   static constexpr int HP = HW + 8;                           // H0 row pitch
   static constexpr int TP = ((HH + 3) & ~3) + 8;              // H0^T row pitch
-  static constexpr int IMG_W = RHA * RP / 4 + 4;              // dwords
+  static constexpr int IMG_W = TH * TPITCH / 4 + 4;           // dwords
   static constexpr int H0_W = HH * HP / 4 + 4;
   static constexpr int H0T_W = HW * TP / 4 + 4;
+  static_assert(NT % 4 == 0, "tiles per workgroup must split over 4 waves");
 };
 
 struct Region {
   int W, H;            // image sides
-  int ax0, ay0;        // region origin (pixels), multiples of 8
+  int ax0, ay0;        // H0 region origin (pixels), multiples of 8
+  int X0, Y0;          // tile block origin (pixels)
   int tx0, ty0, gx;    // first tile of the block, tiles per block row
   int tiles_x;
   uint64_t tile_first;
@@ -66,6 +70,12 @@ __device__ __forceinline__ void range_xy(uint32_t meta, const Region& r, int& X,
   Y = (r.ty0 + tly) * BMAX + (int)((meta >> 8) & 0xffu) * BMIN;
 }
 
+__device__ __forceinline__ uint64_t tile_global(uint32_t meta, const Region& r) {
+  const int tile = (int)(meta >> 16);
+  const int tly = tile / r.gx, tlx = tile - tly * r.gx;
+  return r.tile_first + (uint64_t)(r.ty0 + tly) * r.tiles_x + (uint64_t)(r.tx0 + tlx);
+}
+
 __device__ __forceinline__ int morton(uint32_t meta) {
   const int cx = meta & 0xff, cy = (meta >> 8) & 0xff;
   int code = 0;
@@ -77,25 +87,14 @@ __device__ __forceinline__ int morton(uint32_t meta) {
   return code;
 }
 
-// Stream compaction over the workgroup: returns the exclusive position of
-// this lane's flag within the current 256-lane chunk, and the chunk total.
-__device__ __forceinline__ uint32_t block_prefix(bool flag, uint32_t* s_wsum, uint32_t& total) {
-  const uint64_t bal = __ballot(flag);
-  const uint32_t lane_pre =
-      __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) s_wsum[wave] = (uint32_t)__popcll(bal);
-  __syncthreads();
-  uint32_t off = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const uint32_t v = s_wsum[w];
-    off += (w < wave) ? v : 0u;
-    tot += v;
-  }
-  __syncthreads();
-  total = tot;
-  return off + lane_pre;
+// Make this wave's LDS writes visible to its own later reads (the lanes of
+// one wave exchange data through LDS; no other wave is involved).  The
+// fences are restricted to LDS so that outstanding global stores (records)
+// are not waited for.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int BMAX, int L, int GX, int GY>
@@ -104,23 +103,25 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   __shared__ uint32_t s_img[G::IMG_W];
   __shared__ uint32_t s_h0[G::H0_W];
   __shared__ uint32_t s_h0t[G::H0T_W];
-  __shared__ uint32_t s_meta[2][G::CAP];
-  __shared__ uint32_t s_fit[G::CAP];
-  __shared__ uint32_t s_mom[5][G::CAP];
-  __shared__ uint32_t s_pmeta[G::PCAP];
-  __shared__ uint32_t s_pm[G::PCAP];
+  __shared__ uint32_t s_meta[4][2][G::CAPW];
+  __shared__ uint32_t s_fit[4][G::CAPW];
+  __shared__ uint32_t s_mom[4][5][G::CAPW];
+  __shared__ uint32_t s_pmeta[4][G::PCAPW];
+  __shared__ uint32_t s_pm[4][G::PCAPW];
   __shared__ unsigned long long s_mask[G::NT];
-  __shared__ uint32_t s_wsum[4];
 
   // XCD-aware order: consecutive logical blocks share an XCD (and its L2).
   const uint32_t per = (a.n_wg + 7u) >> 3;
   const uint32_t wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   if (wg >= a.n_wg) return;
-  int lo = 0, hi = (int)a.n_imgs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.imgs[mid].wg_first <= wg) lo = mid; else hi = mid - 1;
+  // image of this block: the number of images starting at or before it,
+  // counted with independent vector loads (no dependent search chain)
+  int lo = -1;
+  for (uint32_t k0 = 0; k0 < a.n_imgs; k0 += 64u) {
+    const uint32_t k = k0 + (threadIdx.x & 63u);
+    lo += (int)__popcll(__ballot(k < a.n_imgs && a.wg_first[k] <= wg));
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);
   const ImgDev im = a.imgs[lo];
   const uint32_t local = wg - im.wg_first;
   const int gyi = (int)(local / im.groups_x), gxi = (int)(local - (uint32_t)gyi * im.groups_x);
@@ -133,87 +134,103 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   const int gy = min(GY, (int)im.tiles_y - rg.ty0);
   rg.tiles_x = (int)im.tiles_x;
   rg.tile_first = im.tile_first;
+  rg.X0 = rg.tx0 * BMAX;
+  rg.Y0 = rg.ty0 * BMAX;
   const int ntiles = rg.gx * gy;
   const int tid = threadIdx.x;
 
-  // ---- 1. stage the region and its 2x2 mean image
-  const int rx0 = clampi(rg.tx0 * BMAX - BMAX / 2, 0, rg.W - 2 * BMAX);
+  // ---- 1. stage the tile pixels and the 2x2 mean image of the domain region
+  const int rx0 = clampi(rg.X0 - BMAX / 2, 0, rg.W - 2 * BMAX);
   const int rx1 = clampi((rg.tx0 + rg.gx - 1) * BMAX - BMAX / 2, 0, rg.W - 2 * BMAX) + 2 * BMAX;
-  const int ry0 = clampi(rg.ty0 * BMAX - BMAX / 2, 0, rg.H - 2 * BMAX);
+  const int ry0 = clampi(rg.Y0 - BMAX / 2, 0, rg.H - 2 * BMAX);
   const int ry1 = clampi((rg.ty0 + gy - 1) * BMAX - BMAX / 2, 0, rg.H - 2 * BMAX) + 2 * BMAX;
   rg.ax0 = rx0 & ~7;
   rg.ay0 = ry0 & ~7;
   const int n8 = (rx1 - rg.ax0 + 7) >> 3;
   const int hrows = (ry1 - rg.ay0) >> 1;
+  const int tx_end = rg.X0 + rg.gx * BMAX, ty_end = rg.Y0 + gy * BMAX;
   uint8_t* h0t_b = reinterpret_cast<uint8_t*>(s_h0t);
   for (int idx = tid; idx < hrows * n8; idx += 256) {
     const int hr = idx / n8, c8 = idx - hr * n8;
-    const int x = rg.ax0 + 8 * c8;
-    const uint8_t* p0 = im.data + (size_t)(rg.ay0 + 2 * hr) * im.stride + x;
-    const uint8_t* p1 = p0 + im.stride;
+    const int x = rg.ax0 + 8 * c8, y = rg.ay0 + 2 * hr;
+    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(im.data + (size_t)y * im.stride + x);
+    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(im.data + (size_t)(y + 1) * im.stride + x);
     uint32_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
     if (x + 8 <= rg.W) {
-      const uint2 u = *reinterpret_cast<const uint2*>(p0);
-      const uint2 v = *reinterpret_cast<const uint2*>(p1);
-      a0 = u.x; a1 = u.y; b0 = v.x; b1 = v.y;
+      a0 = p0[0]; a1 = p0[1]; b0 = p1[0]; b1 = p1[1];
     } else if (x < rg.W) {
-      a0 = *reinterpret_cast<const uint32_t*>(p0);
-      b0 = *reinterpret_cast<const uint32_t*>(p1);
+      a0 = p0[0]; b0 = p1[0];
     }
-    s_img[(2 * hr) * (G::RP / 4) + 2 * c8] = a0;
-    s_img[(2 * hr) * (G::RP / 4) + 2 * c8 + 1] = a1;
-    s_img[(2 * hr + 1) * (G::RP / 4) + 2 * c8] = b0;
-    s_img[(2 * hr + 1) * (G::RP / 4) + 2 * c8 + 1] = b1;
-    const uint32_t h = mean2x2_x4(a0, a1, b0, b1);
-    s_h0[hr * (G::HP / 4) + c8] = h;
-    h0t_b[(4 * c8 + 0) * G::TP + hr] = (uint8_t)h;
-    h0t_b[(4 * c8 + 1) * G::TP + hr] = (uint8_t)(h >> 8);
-    h0t_b[(4 * c8 + 2) * G::TP + hr] = (uint8_t)(h >> 16);
-    h0t_b[(4 * c8 + 3) * G::TP + hr] = (uint8_t)(h >> 24);
+    // tile pixels (dword granularity: tile edges are multiples of 4)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int xx = x + 4 * h;
+      if (xx >= rg.X0 && xx < tx_end) {
+        const int col = (xx - rg.X0) >> 2;
+        if (y >= rg.Y0 && y < ty_end) s_img[(y - rg.Y0) * (G::TPITCH / 4) + col] = h ? a1 : a0;
+        if (y + 1 >= rg.Y0 && y + 1 < ty_end) s_img[(y + 1 - rg.Y0) * (G::TPITCH / 4) + col] = h ? b1 : b0;
+      }
+    }
+    const uint32_t hv = mean2x2_x4(a0, a1, b0, b1);
+    s_h0[hr * (G::HP / 4) + c8] = hv;
+    h0t_b[(4 * c8 + 0) * G::TP + hr] = (uint8_t)hv;
+    h0t_b[(4 * c8 + 1) * G::TP + hr] = (uint8_t)(hv >> 8);
+    h0t_b[(4 * c8 + 2) * G::TP + hr] = (uint8_t)(hv >> 16);
+    h0t_b[(4 * c8 + 3) * G::TP + hr] = (uint8_t)(hv >> 24);
   }
   for (int t = tid; t < G::NT; t += 256) s_mask[t] = 0ull;
-  for (int t = tid; t < ntiles; t += 256) s_meta[0][t] = (uint32_t)t << 16;
   __syncthreads();
 
-  int n = ntiles;  // ranges in the current list (uniform)
+  // ---- 2. each wave runs the quadtree of its own tiles, independently
+  const int wave = tid >> 6, lane = tid & 63;
+  const int t_first = wave * G::NTW;
+  const int my_tiles = max(0, min(G::NTW, ntiles - t_first));
+  if (my_tiles == 0) return;
+  uint32_t* w_meta0 = s_meta[wave][0];
+  uint32_t* w_meta1 = s_meta[wave][1];
+  uint32_t* w_fit = s_fit[wave];
+  uint32_t* w_pmeta = s_pmeta[wave];
+  uint32_t* w_pm = s_pm[wave];
+  if (lane < my_tiles) w_meta0[lane] = (uint32_t)(t_first + lane) << 16;
+  wave_sync();
+
+  int n = my_tiles;  // ranges in the current list (wave-uniform)
   for (int lev = 1; lev <= L; ++lev) {
-    const int cb = (lev - 1) & 1;
+    uint32_t* cur = (lev & 1) ? w_meta0 : w_meta1;
+    uint32_t* nxt = (lev & 1) ? w_meta1 : w_meta0;
     const bool last = lev == L;
     const uint32_t thr = last ? 0u : a.thr[lev - 1];
     const int B = BMAX >> (lev - 1);
 
-    // ---- 2. moments + phase-1 fit of the listed ranges
+    // moments + phase-1 fit of the listed ranges (team of T lanes per range)
     auto moments_fit = [&](auto bconst) {
       constexpr int BB = decltype(bconst)::value;
       constexpr bool ALIGNED = BB >= 16;
       int T = 1;
-      while (T < BB / 2 && T < 16 && n * (T * 2) <= 256) T *= 2;
+      while (T < BB / 2 && T < 16 && n * (T * 2) <= 64) T *= 2;
       const int logT = __builtin_ctz((unsigned)T);
-      for (int base = 0; base < n * T; base += 256) {
-        const int idx = base + tid;
+      for (int base = 0; base < n * T; base += 64) {
+        const int idx = base + lane;
         const int e = idx >> logT, t = idx & (T - 1);
         uint32_t acc[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] = 0u;
         if (e < n) {
           int X, Y;
-          range_xy<BMAX, G::BMIN>(s_meta[cb][e], rg, X, Y);
+          range_xy<BMAX, G::BMIN>(cur[e], rg, X, Y);
           const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
           const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
-          const int rx = X - rg.ax0, ry = Y - rg.ay0;
+          const int rx = X - rg.X0, ry = Y - rg.Y0;
           const int wx = (dx - rg.ax0) >> 1, wy = (dy - rg.ay0) >> 1;
           for (int i = t; i < BB / 2; i += T)
-            accumulate_row_pair<BB, ALIGNED>(s_img, ry * G::RP + rx, G::RP, s_h0, wy * G::HP + wx, G::HP,
-                                             s_h0t, wx * G::TP + wy, G::TP, i, acc);
+            accumulate_row_pair<BB, ALIGNED>(s_img, ry * G::TPITCH + rx, G::TPITCH, s_h0, wy * G::HP + wx,
+                                             G::HP, s_h0t, wx * G::TP + wy, G::TP, i, acc);
         }
         team_reduce(acc, T);
         if (e < n && t == 0) {
-          s_fit[e] = fit_phase1<BB>(acc, last, thr);
-          s_mom[0][e] = acc[0];
-          s_mom[1][e] = acc[1];
-          s_mom[2][e] = acc[2];
-          s_mom[3][e] = acc[3];
-          s_mom[4][e] = acc[4];
+          w_fit[e] = fit_phase1<BB>(acc, last, thr);
+#pragma unroll
+          for (int s = 0; s < 5; ++s) s_mom[wave][s][e] = acc[s];
         }
       }
     };
@@ -221,102 +238,95 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
     if constexpr (BMAX >= 16 && G::BMIN <= 16) { if (B == 16) moments_fit(std::integral_constant<int, 16>{}); }
     if constexpr (BMAX >= 8 && G::BMIN <= 8) { if (B == 8) moments_fit(std::integral_constant<int, 8>{}); }
     if constexpr (G::BMIN <= 4) { if (B == 4) moments_fit(std::integral_constant<int, 4>{}); }
-    __syncthreads();
+    wave_sync();
 
-    // ---- 3. phase 2 of the parents that failed at level lev-1
+    // phase 2 of the parents that failed at level lev-1 (their children are
+    // exactly the ranges just fitted, four per parent in Z order)
     if (lev >= 2 && a.phase2) {
       const int np = n >> 2;
       auto phase2 = [&](auto bconst) {
         constexpr int BB = decltype(bconst)::value;   // child side
-        for (int p = tid; p < np; p += 256) {
+        for (int p = lane; p < np; p += 64) {
           uint32_t mom[4][5];
 #pragma unroll
           for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int s = 0; s < 5; ++s) mom[c][s] = s_mom[s][4 * p + c];
-          const int m = (int)s_pm[p];
+            for (int s = 0; s < 5; ++s) mom[c][s] = s_mom[wave][s][4 * p + c];
+          const int m = (int)w_pm[p];
           int O[4];
           uint32_t bits;
-          const bool ok = fit_phase2<BB>(mom, m, lev - 1, a.thr[lev - 2], O, bits);
-          if (ok) {
-            const uint32_t pmeta = s_pmeta[p];
+          if (fit_phase2<BB>(mom, m, lev - 1, a.thr[lev - 2], O, bits)) {
+            const uint32_t pmeta = w_pmeta[p];
             int X, Y;
             range_xy<BMAX, G::BMIN>(pmeta, rg, X, Y);
             const int PB = 2 * BB;
             const int dx = clampi(X - PB / 2, 0, rg.W - 2 * PB);
             const int dy = clampi(Y - PB / 2, 0, rg.H - 2 * PB);
-            const uint4 rec = make_record(X, Y, dx, dy, lev - 2, 1, 0, (int)bits, m, O[0] - m, O[1] - m,
-                                          O[2] - m);
-            const int tile = (int)(pmeta >> 16);
-            const int tly = tile / rg.gx, tlx = tile - tly * rg.gx;
-            const uint64_t tg = rg.tile_first + (uint64_t)(rg.ty0 + tly) * rg.tiles_x + (rg.tx0 + tlx);
             const int cell = morton(pmeta);
-            a.staging[tg * G::CELLS + cell] = rec;
-            atomicOr(&s_mask[tile], 1ull << cell);
+            a.staging[tile_global(pmeta, rg) * G::CELLS + cell] =
+                make_record(X, Y, dx, dy, lev - 2, 1, 0, (int)bits, m, O[0] - m, O[1] - m, O[2] - m);
+            atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s_fit[4 * p + c] |= kFitDead;
+            for (int c = 0; c < 4; ++c) w_fit[4 * p + c] |= kFitDead;
           }
         }
       };
       if constexpr (BMAX >= 32 && G::BMIN <= 16) { if (B == 16) phase2(std::integral_constant<int, 16>{}); }
       if constexpr (BMAX >= 16 && G::BMIN <= 8) { if (B == 8) phase2(std::integral_constant<int, 8>{}); }
       if constexpr (BMAX >= 8 && G::BMIN <= 4) { if (B == 4) phase2(std::integral_constant<int, 4>{}); }
-      __syncthreads();
+      wave_sync();
     }
 
-    // ---- 4. store accepted ranges; compact failures into the next level
+    // store accepted ranges; compact failures (ballot prefix) into the
+    // parent list and their children into the next level's list
     uint32_t nfail = 0;
-    for (int base = 0; base < n; base += 256) {
-      const int e = base + tid;
+    for (int base = 0; base < n; base += 64) {
+      const int e = base + lane;
       bool fail = false;
       uint32_t meta = 0, fit = 0;
       if (e < n) {
-        meta = s_meta[cb][e];
-        fit = s_fit[e];
+        meta = cur[e];
+        fit = w_fit[e];
         if (!(fit & kFitDead)) {
           if (fit & kFitAccept) {
             int X, Y;
             range_xy<BMAX, G::BMIN>(meta, rg, X, Y);
             const int dx = clampi(X - B / 2, 0, rg.W - 2 * B);
             const int dy = clampi(Y - B / 2, 0, rg.H - 2 * B);
-            const uint4 rec = make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u),
-                                          (int)((fit >> 8) & 7u), (int)(fit & 0xffu), 0, 0, 0);
-            const int tile = (int)(meta >> 16);
-            const int tly = tile / rg.gx, tlx = tile - tly * rg.gx;
-            const uint64_t tg = rg.tile_first + (uint64_t)(rg.ty0 + tly) * rg.tiles_x + (rg.tx0 + tlx);
             const int cell = morton(meta);
-            a.staging[tg * G::CELLS + cell] = rec;
-            atomicOr(&s_mask[tile], 1ull << cell);
+            a.staging[tile_global(meta, rg) * G::CELLS + cell] =
+                make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
+                            (int)(fit & 0xffu), 0, 0, 0);
+            atomicOr(&s_mask[meta >> 16], 1ull << cell);
           } else {
             fail = true;
           }
         }
       }
-      uint32_t total;
-      const uint32_t q = nfail + block_prefix(fail, s_wsum, total);
+      const uint64_t bal = __ballot(fail);
+      const uint32_t q = nfail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
       if (fail) {
-        s_pmeta[q] = meta;
-        s_pm[q] = fit & 0xffu;
+        w_pmeta[q] = meta;
+        w_pm[q] = fit & 0xffu;
         const uint32_t half = (uint32_t)(B / 2 / G::BMIN);
         const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
 #pragma unroll
         for (uint32_t c = 0; c < 4; ++c)
-          s_meta[cb ^ 1][4 * q + c] = tile | ((cy + (c >> 1) * half) << 8) | (cx + (c & 1u) * half);
+          nxt[4 * q + c] = tile | ((cy + (c >> 1) * half) << 8) | (cx + (c & 1u) * half);
       }
-      nfail += total;
+      nfail += (uint32_t)__popcll(bal);
     }
-    __syncthreads();
+    wave_sync();
     n = (int)(4 * nfail);
     if (last || n == 0) break;
   }
 
-  // ---- publish per-tile occupancy and counts
-  for (int t = tid; t < ntiles; t += 256) {
-    const int tly = t / rg.gx, tlx = t - tly * rg.gx;
-    const uint64_t tg = rg.tile_first + (uint64_t)(rg.ty0 + tly) * rg.tiles_x + (rg.tx0 + tlx);
-    const unsigned long long mk = s_mask[t];
-    a.masks[tg] = mk;
-    atomicAdd(&a.chunk_sum[tg / kChunkTiles], (uint32_t)__popcll(mk));
+  // ---- publish the wave's tiles' occupancy masks
+  wave_sync();
+  if (lane < my_tiles) {
+    const uint32_t meta = (uint32_t)(t_first + lane) << 16;
+    a.masks[tile_global(meta, rg)] = s_mask[t_first + lane];
   }
 }
 
@@ -325,64 +335,121 @@ __global__ void zero_u32_kernel(uint32_t* p, size_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// One workgroup per kChunkTiles consecutive tiles (global order = image,
-// then tile raster).  Record k of tile t goes to the stream position
-// (records of all earlier tiles) + (rank of its Morton cell among t's).
-__global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
-                                                     uint64_t total_tiles, int cells,
-                                                     const uint64_t* masks, const uint32_t* chunk_sum,
-                                                     const uint4* staging, uint4* out, uint64_t cap,
-                                                     uint64_t* offsets) {
-  __shared__ unsigned long long s_red[256];
-  __shared__ uint32_t s_scan[256];
-  __shared__ unsigned long long s_tbase[kChunkTiles];
-  const int tid = threadIdx.x;
-  const uint64_t c0 = (uint64_t)blockIdx.x * kChunkTiles;
-  unsigned long long acc = 0;
-  for (uint32_t i = tid; i < blockIdx.x; i += 256) acc += chunk_sum[i];
-  s_red[tid] = acc;
+// Records per chunk of kChunkTiles tiles (one lane per tile).
+__global__ __launch_bounds__(kChunkTiles) void chunk_count_kernel(const uint64_t* masks, uint64_t total_tiles,
+                                                                 uint32_t* chunk_sum) {
+  __shared__ uint32_t s_w[kChunkTiles / 64];
+  const uint64_t tile = (uint64_t)blockIdx.x * kChunkTiles + threadIdx.x;
+  uint32_t c = tile < total_tiles ? (uint32_t)__popcll(masks[tile]) : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) s_red[tid] += s_red[tid + s];
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kChunkTiles / 64; ++w) t += s_w[w];
+    chunk_sum[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the chunk counts (one workgroup): chunk_base[c] =
+// records of all chunks before c; chunk_base[n] = total.
+__global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* chunk_sum, uint32_t n,
+                                                         uint64_t* chunk_base) {
+  __shared__ unsigned long long s_w[16];
+  __shared__ unsigned long long s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < n; c0 += 1024) {
+    const uint32_t c = c0 + tid;
+    const unsigned long long v = c < n ? chunk_sum[c] : 0ull;
+    unsigned long long incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned long long u = __shfl_up(incl, off);
+      if (lane >= off) incl += u;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    unsigned long long pre = s_carry;
+    for (int w = 0; w < wave; ++w) pre += s_w[w];
+    if (c < n) chunk_base[c] = pre + incl - v;
+    __syncthreads();
+    if (tid == 1023) s_carry = pre + incl;
     __syncthreads();
   }
-  const unsigned long long base = s_red[0];
+  if (tid == 0) chunk_base[n] = s_carry;
+}
+
+// One workgroup per kChunkTiles consecutive tiles (global order = image,
+// then tile raster).  Stream position of a record = records of all earlier
+// tiles + rank of its Morton cell among its tile's cells.  The workgroup
+// scans its tiles' counts, then copies its contiguous output range with one
+// record per lane (coalesced writes), locating each record's tile by binary
+// search over the tile bases.
+__global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
+                                                     uint64_t total_tiles, int cells,
+                                                     const uint64_t* masks, const uint64_t* chunk_base,
+                                                     const uint4* staging, uint4* out, uint64_t cap,
+                                                     uint64_t* offsets) {
+  __shared__ uint32_t s_wsum[4];
+  __shared__ uint32_t s_tbase[kChunkTiles + 1];
+  __shared__ unsigned long long s_mk[kChunkTiles];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t c0 = (uint64_t)blockIdx.x * kChunkTiles;
+  const unsigned long long base = chunk_base[blockIdx.x];
   constexpr int PER = kChunkTiles / 256;
-  unsigned long long mk[PER];
+  uint32_t cnt[PER];
   uint32_t tsum = 0;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const uint64_t tile = c0 + (uint64_t)tid * PER + j;
-    mk[j] = tile < total_tiles ? masks[tile] : 0ull;
-    tsum += (uint32_t)__popcll(mk[j]);
+    const unsigned long long m = tile < total_tiles ? masks[tile] : 0ull;
+    s_mk[tid * PER + j] = m;
+    cnt[j] = (uint32_t)__popcll(m);
+    tsum += cnt[j];
   }
-  s_scan[tid] = tsum;
+  // exclusive scan of tsum over the 256 lanes
+  uint32_t incl = tsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) s_wsum[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
-    __syncthreads();
-    s_scan[tid] += v;
-    __syncthreads();
+  uint32_t wpre = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    wpre += w < wave ? s_wsum[w] : 0u;
+    total += s_wsum[w];
   }
-  unsigned long long pos = base + s_scan[tid] - tsum;
+  uint32_t pos = wpre + incl - tsum;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const uint64_t tile = c0 + (uint64_t)tid * PER + j;
     s_tbase[tid * PER + j] = pos;
-    unsigned long long m = mk[j];
-    while (m) {
-      const int b = __builtin_ctzll(m);
-      m &= m - 1;
-      if (pos < cap) out[pos] = staging[tile * (uint64_t)cells + b];
-      ++pos;
-    }
+    pos += cnt[j];
   }
+  if (tid == 0) s_tbase[kChunkTiles] = total;
   __syncthreads();
+  for (uint32_t r = tid; r < total; r += 256) {
+    int lo = 0, hi = kChunkTiles - 1;      // last tile with base <= r
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_tbase[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    unsigned long long m = s_mk[lo];
+    for (uint32_t k = r - s_tbase[lo]; k > 0; --k) m &= m - 1;
+    const int cell = __builtin_ctzll(m);
+    const unsigned long long o = base + r;
+    if (o < cap) out[o] = staging[(c0 + lo) * (uint64_t)cells + cell];
+  }
   for (uint32_t k = tid; k < n_imgs; k += 256) {
     const uint64_t tf = imgs[k].tile_first;
-    if (tf >= c0 && tf < c0 + kChunkTiles) offsets[k] = s_tbase[tf - c0];
+    if (tf >= c0 && tf < c0 + kChunkTiles) offsets[k] = base + s_tbase[tf - c0];
   }
-  if (blockIdx.x == gridDim.x - 1 && tid == 255) offsets[n_imgs] = pos;
+  if (blockIdx.x == gridDim.x - 1 && tid == 0) offsets[n_imgs] = base + total;
 }
 
 }  // namespace
@@ -429,11 +496,13 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, uint64_t total_tiles, int cells,
-                          const uint64_t* masks, const uint32_t* chunk_sum, const uint4* staging, uint4* out,
-                          uint64_t cap, uint64_t* offsets, hipStream_t s) {
+                          const uint64_t* masks, uint32_t* chunk_sum, uint64_t* chunk_base, const uint4* staging,
+                          uint4* out, uint64_t cap, uint64_t* offsets, hipStream_t s) {
   const unsigned grid = (unsigned)((total_tiles + kChunkTiles - 1) / kChunkTiles);
+  hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(kChunkTiles), 0, s, masks, total_tiles, chunk_sum);
+  hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, chunk_sum, grid, chunk_base);
   hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, total_tiles, cells, masks,
-                     chunk_sum, staging, out, cap, offsets);
+                     chunk_base, staging, out, cap, offsets);
   return hipGetLastError();
 }
 
