@@ -246,6 +246,31 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
                     uint8_t* d_out, void* stream);
 
 /*
+ * Tile shapes of the fused encode kernel.  A workgroup runs the quadtrees of
+ * a gx x gy block of top-level tiles (b_max x b_max each); the shape trades
+ * LDS per workgroup (occupancy) against the halo of domain pixels staged
+ * around the block.  fe_tile_shapes lists the shapes built for (b_max,
+ * b_min) (first = default) and returns their number (at most max_out
+ * written).  fe_set_tile_shape selects one for a context (gx = gy = 0
+ * restores the default); FE_ERR_INVALID if the shape is not built.  The
+ * encoded stream does not depend on the shape.
+ */
+int fe_tile_shapes(uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy, int max_out);
+fe_status fe_set_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_t gx, uint32_t gy);
+fe_status fe_get_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy);
+
+/*
+ * Autotuner: encode the given batch (as fe_encode_batch, into the caller's
+ * d_out / d_offsets) `reps` times with every built tile shape for
+ * (b_max, b_min), time the fused kernel with HIP events on `stream`, and
+ * select the fastest for this context.  Writes the chosen shape and its
+ * mean kernel time in milliseconds.  Waits for the device.
+ */
+fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* params,
+                      fe_transform* d_out, size_t cap, uint64_t* d_offsets, uint32_t reps, uint32_t* gx,
+                      uint32_t* gy, double* ms, void* stream);
+
+/*
  * Kernel timing.  While enabled, each launch of the library's main kernels
  * (below) is bracketed by HIP events recorded on the launch's own stream.
  * fe_timing_read waits for those events, adds each kernel's event-to-event

@@ -71,6 +71,12 @@ _SIGNATURES = {
     "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
+    "fe_tile_shapes": (ctypes.c_int, [_U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.c_int]),
+    "fe_set_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, _U32, _U32]),
+    "fe_get_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
+    "fe_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params), _VP, _SZ,
+                                   _VP, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32),
+                                   ctypes.POINTER(ctypes.c_double), _VP]),
     "fe_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "fe_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                       _U32]),
@@ -223,6 +229,42 @@ def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: 
     _check(load().fe_decode(ctx, _ptr(transforms), n, width, height, b_max, iters, _ptr(start), _ptr(out),
                             _stream(stream)))
     return out
+
+
+def fe_tile_shapes(b_max: int, b_min: int):
+    gx = (_U32 * 16)()
+    gy = (_U32 * 16)()
+    k = load().fe_tile_shapes(b_max, b_min, gx, gy, 16)
+    return [(gx[i], gy[i]) for i in range(min(k, 16))]
+
+
+def fe_set_tile_shape(ctx: int, b_max: int, b_min: int, gx: int, gy: int) -> None:
+    _check(load().fe_set_tile_shape(ctx, b_max, b_min, gx, gy))
+
+
+def fe_get_tile_shape(ctx: int, b_max: int, b_min: int):
+    gx, gy = _U32(0), _U32(0)
+    _check(load().fe_get_tile_shape(ctx, b_max, b_min, ctypes.byref(gx), ctypes.byref(gy)))
+    return gx.value, gy.value
+
+
+def _descs(imgs):
+    descs = (fe_image_desc * len(imgs))()
+    for k, im in enumerate(imgs):
+        H, W = im.shape
+        descs[k].data = _ptr(im)
+        descs[k].width, descs[k].height, descs[k].stride, descs[k].reserved = W, H, im.stride(0), 0
+    return descs
+
+
+def fe_autotune(ctx: int, imgs, params: fe_params, out, offsets, reps: int = 3, stream=None):
+    """Time every built tile shape on this batch; the fastest is selected
+    for the context.  Returns ((gx, gy), kernel ms)."""
+    gx, gy, ms = _U32(0), _U32(0), ctypes.c_double(0)
+    _check(load().fe_autotune(ctx, _descs(imgs), len(imgs), ctypes.byref(params), _ptr(out), out.shape[0],
+                              _ptr(offsets), reps, ctypes.byref(gx), ctypes.byref(gy), ctypes.byref(ms),
+                              _stream(stream)))
+    return (gx.value, gy.value), ms.value
 
 
 def fe_timing_enable(ctx: int, enable: bool = True) -> None:

@@ -13,6 +13,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
@@ -23,7 +24,8 @@ HIP_SOURCES = ["mns_encode.hip", "mns_steps.hip", "decode.hip", "fullsearch.hip"
 # not know the feature and warns, which is harmless.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas"]
+               "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas",
+               "-I" + INCLUDE]
 
 
 def hipcc() -> str:

@@ -5,7 +5,7 @@
 
 #include <string>
 
-#include "../../include/fe.h"
+#include "fe.h"
 #include "fe_common.h"
 
 namespace fe {

@@ -3,7 +3,7 @@
 
 #include <stdint.h>
 
-#include "../../include/fe.h"
+#include "fe.h"
 
 namespace fe {
 

@@ -143,9 +143,11 @@ __device__ __forceinline__ uint32_t fit_phase1(const uint32_t (&m)[12], bool for
   const double Q = N * sdd - sd * sd;
   const double P = N * (double)best - sr * sd;
   const double P16 = 16.0 * P;
-  int k = 0;
-#pragma unroll
-  for (int j = 0; j < 7; ++j) k += ((double)(2 * j + 1) * Q < P16) ? 1 : 0;
+  // k = #{j in 0..6 : (2j+1) Q < 16 P}; the predicate is monotone in j, so
+  // three tests of a binary search find the count
+  int k = (7.0 * Q < P16) ? 4 : 0;
+  k += ((double)(2 * k + 3) * Q < P16) ? 2 : 0;
+  k += ((double)(2 * k + 1) * Q < P16) ? 1 : 0;
   if (k == 0) e = 0;
   const double kd = (double)k;
   const double f = (kd * kd) * Q - (16.0 * kd) * P;

@@ -6,7 +6,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "../../include/fe.h"
+#include "fe.h"
 #include "fe_common.h"
 #include "fe_internal.h"
 
@@ -26,6 +26,8 @@ struct fe_ctx {
   size_t chunk_n = 0;
   uint64_t* chunk_base = nullptr;
   size_t chunk_base_n = 0;
+  fe::BlockDesc* blocks = nullptr;
+  size_t blocks_n = 0;
   uint64_t* offsets = nullptr;
   size_t offsets_n = 0;
   uint32_t* flags = nullptr;          // small device counters
@@ -167,6 +169,7 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
+  if ((st = ensure(ctx->blocks, ctx->blocks_n, (size_t)wgs, "block descriptors")) != FE_OK) return st;
   uint64_t* offsets = d_offsets;
   if (!offsets) {
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
@@ -174,9 +177,11 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   }
   if ((st = upload_table(ctx, table.data(), n_imgs, s)) != FE_OK) return st;
 
+  FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, ctx->blocks, s), "prep launch");
   fe::EncodeArgs a{};
   a.imgs = ctx->d_table;
   a.wg_first = reinterpret_cast<const uint32_t*>(ctx->d_table + n_imgs);
+  a.blocks = ctx->blocks;
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
   a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
@@ -246,6 +251,7 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->masks);
   (void)hipFree(c->chunk_sum);
   (void)hipFree(c->chunk_base);
+  (void)hipFree(c->blocks);
   (void)hipFree(c->offsets);
   (void)hipFree(c->flags);
   (void)hipFree(c->tmp_img);
@@ -341,6 +347,92 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
     Timed tm(ctx, FE_TIMING_DECODE, s);
     FE_HIP(fe::launch_decode_iter(a, buf[s0 ^ (int)(t & 1u)], buf[s0 ^ (int)((t + 1) & 1u)], s), "decode launch");
   }
+  return FE_OK;
+}
+
+int fe_tile_shapes(uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy, int max_out) {
+  if (!fe::is_pow2(b_max) || !fe::is_pow2(b_min) || b_min < 4 || b_max > 32 || b_min > b_max) return 0;
+  fe::TileShape shapes[16];
+  const int k = fe::encode_shapes((int)b_max, fe::levels_of(b_max, b_min), shapes, 16);
+  for (int i = 0; i < k && i < max_out; ++i) {
+    if (gx) gx[i] = (uint32_t)shapes[i].gx;
+    if (gy) gy[i] = (uint32_t)shapes[i].gy;
+  }
+  return k;
+}
+
+fe_status fe_set_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_t gx, uint32_t gy) {
+  fe::clear_error();
+  if (!ctx) return fe::fail(FE_ERR_INVALID, "NULL context");
+  const int n = fe_tile_shapes(b_max, b_min, nullptr, nullptr, 0);
+  if (n == 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%u b_min=%u", b_max, b_min);
+  const int L = fe::levels_of(b_max, b_min);
+  if (gx == 0 && gy == 0) {
+    ctx->shape_override[b_max][L] = fe::TileShape{0, 0};
+    return FE_OK;
+  }
+  fe::TileShape shapes[16];
+  const int k = fe::encode_shapes((int)b_max, L, shapes, 16);
+  for (int i = 0; i < k; ++i) {
+    if ((uint32_t)shapes[i].gx == gx && (uint32_t)shapes[i].gy == gy) {
+      ctx->shape_override[b_max][L] = shapes[i];
+      return FE_OK;
+    }
+  }
+  return fe::fail(FE_ERR_INVALID, "tile shape %ux%u is not built for b_max=%u b_min=%u", gx, gy, b_max, b_min);
+}
+
+fe_status fe_get_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy) {
+  fe::clear_error();
+  if (!ctx || !gx || !gy) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (fe_tile_shapes(b_max, b_min, nullptr, nullptr, 0) == 0)
+    return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%u b_min=%u", b_max, b_min);
+  const fe::TileShape t = pick_shape(ctx, (int)b_max, fe::levels_of(b_max, b_min));
+  *gx = (uint32_t)t.gx;
+  *gy = (uint32_t)t.gy;
+  return FE_OK;
+}
+
+fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p,
+                      fe_transform* d_out, size_t cap, uint64_t* d_offsets, uint32_t reps, uint32_t* gx,
+                      uint32_t* gy, double* ms, void* stream) {
+  fe::clear_error();
+  if (!ctx || !gx || !gy || !ms || reps == 0) return fe::fail(FE_ERR_INVALID, "bad arguments");
+  fe_status st = fe::check_params(p);
+  if (st != FE_OK) return st;
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  fe::TileShape shapes[16];
+  const int k = fe::encode_shapes((int)p->b_max, L, shapes, 16);
+  const bool was_timing = ctx->timing;
+  double best = 1e30;
+  fe::TileShape best_shape{0, 0};
+  for (int i = 0; i < k; ++i) {
+    ctx->shape_override[p->b_max][L] = shapes[i];
+    st = fe_encode_batch(ctx, h_imgs, n_imgs, p, d_out, cap, d_offsets, nullptr, stream);   // warm-up
+    if (st != FE_OK) break;
+    double t_ms[FE_TIMING_SLOTS];
+    uint64_t cnt[FE_TIMING_SLOTS];
+    if ((st = fe_timing_read(ctx, t_ms, cnt, FE_TIMING_SLOTS)) != FE_OK) break;
+    if ((st = fe_timing_enable(ctx, 1)) != FE_OK) break;
+    for (uint32_t r = 0; r < reps && st == FE_OK; ++r)
+      st = fe_encode_batch(ctx, h_imgs, n_imgs, p, d_out, cap, d_offsets, nullptr, stream);
+    if (st != FE_OK) break;
+    if ((st = fe_timing_read(ctx, t_ms, cnt, FE_TIMING_SLOTS)) != FE_OK) break;
+    const double mean = cnt[FE_TIMING_ENCODE] ? t_ms[FE_TIMING_ENCODE] / (double)cnt[FE_TIMING_ENCODE] : 1e30;
+    if (mean < best) {
+      best = mean;
+      best_shape = shapes[i];
+    }
+  }
+  ctx->timing = was_timing;
+  if (st != FE_OK) {
+    ctx->shape_override[p->b_max][L] = fe::TileShape{0, 0};
+    return st;
+  }
+  ctx->shape_override[p->b_max][L] = best_shape;
+  *gx = (uint32_t)best_shape.gx;
+  *gy = (uint32_t)best_shape.gy;
+  *ms = best;
   return FE_OK;
 }
 

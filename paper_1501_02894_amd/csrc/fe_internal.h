@@ -18,10 +18,22 @@ struct ImgDev {
   uint64_t tile_first;          // global index of this image's first tile
 };
 
+// One workgroup's block of top tiles, expanded from the image table by the
+// prep kernel so that a workgroup starts with a single 32-byte load.
+struct BlockDesc {
+  const uint8_t* data;  // image
+  uint64_t tg0;         // global index of the block's first tile
+  uint32_t stride;      // image row pitch (bytes)
+  uint32_t wh;          // (width - 1) | (height - 1) << 16
+  uint32_t t0;          // first tile of the block: tx0 | ty0 << 16
+  uint32_t pad;
+};
+
 // Per-call encoder constants (passed by value).
 struct EncodeArgs {
   const ImgDev* imgs;
   const uint32_t* wg_first;  // per image: first logical workgroup (sorted)
+  const BlockDesc* blocks;   // per logical workgroup
   uint32_t n_imgs;
   uint32_t n_wg;       // logical workgroups over all images
   uint32_t phase2;     // run Technique 1
@@ -47,6 +59,11 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
                             hipStream_t stream);
 
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
+
+// Expand the image table into one BlockDesc per logical workgroup for a
+// block of gx x gy tiles of side b_max.
+hipError_t launch_block_prep(const ImgDev* imgs, uint32_t n_imgs, uint32_t n_wg, int b_max, int gx, int gy,
+                             BlockDesc* blocks, hipStream_t stream);
 
 // Count records per chunk of tiles, scan the chunk counts, and copy the
 // records from staging into stream order; writes per-image offsets and the

@@ -26,6 +26,8 @@
 // After the workgroup finishes, its tiles' occupancy masks and record
 // counts are published; a second kernel orders the records into the
 // depth-first stream (tiles in raster order, Morton order inside a tile).
+#include <algorithm>
+
 #include "fe_device.h"
 #include "fe_internal.h"
 
@@ -36,6 +38,7 @@ template <int BMAX, int L, int GX, int GY>
 struct Geo {
   static constexpr int BMIN = BMAX >> (L - 1);
   static constexpr int NT = GX * GY;                          // tiles per workgroup
+  static constexpr int LOG_GX = Log2<GX>::value;
   static constexpr int NTW = NT / 4;                          // tiles per wave
   static constexpr int CELLS = 1 << (2 * (L - 1));
   static constexpr int CAPW = NTW * CELLS;                    // per-wave deepest list bound
@@ -48,7 +51,8 @@ struct Geo {
   static constexpr int HP = HW + 8;                           // H0 row pitch
   static constexpr int TP = ((HH + 3) & ~3) + 8;              // H0^T row pitch
   static constexpr int IMG_W = TH * TPITCH / 4 + 4;           // dwords
-  static constexpr int H0_W = HH * HP / 4 + 4;
+  static constexpr int HH4 = (HH + 3) & ~3;                   // H0 rows, multiple of 4
+  static constexpr int H0_W = HH4 * HP / 4 + 4;
   static constexpr int H0T_W = HW * TP / 4 + 4;
   static_assert(NT % 4 == 0, "tiles per workgroup must split over 4 waves");
 };
@@ -57,23 +61,28 @@ struct Region {
   int W, H;            // image sides
   int ax0, ay0;        // H0 region origin (pixels), multiples of 8
   int X0, Y0;          // tile block origin (pixels)
-  int tx0, ty0, gx;    // first tile of the block, tiles per block row
   int tiles_x;
-  uint64_t tile_first;
+  uint64_t tg0;        // global index of the block's first tile
 };
 
-template <int BMAX, int BMIN>
+// List entry: bits 0-7 cell x, 8-15 cell y (in B_min units inside the tile),
+// bits 16+ tile index t = tly * GX + tlx inside the workgroup's block.
+template <int BMAX, int BMIN, int LOG_GX>
 __device__ __forceinline__ void range_xy(uint32_t meta, const Region& r, int& X, int& Y) {
-  const int tile = (int)(meta >> 16);
-  const int tly = tile / r.gx, tlx = tile - tly * r.gx;
-  X = (r.tx0 + tlx) * BMAX + (int)(meta & 0xffu) * BMIN;
-  Y = (r.ty0 + tly) * BMAX + (int)((meta >> 8) & 0xffu) * BMIN;
+  const int t = (int)(meta >> 16);
+  X = r.X0 + (t & ((1 << LOG_GX) - 1)) * BMAX + (int)(meta & 0xffu) * BMIN;
+  Y = r.Y0 + (t >> LOG_GX) * BMAX + (int)((meta >> 8) & 0xffu) * BMIN;
 }
 
+template <int LOG_GX>
 __device__ __forceinline__ uint64_t tile_global(uint32_t meta, const Region& r) {
-  const int tile = (int)(meta >> 16);
-  const int tly = tile / r.gx, tlx = tile - tly * r.gx;
-  return r.tile_first + (uint64_t)(r.ty0 + tly) * r.tiles_x + (uint64_t)(r.tx0 + tlx);
+  const int t = (int)(meta >> 16);
+  return r.tg0 + (uint64_t)((uint32_t)(t >> LOG_GX) * (uint32_t)r.tiles_x + (uint32_t)(t & ((1 << LOG_GX) - 1)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ int morton(uint32_t meta) {
@@ -97,104 +106,159 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int BMAX, int L, int GX, int GY>
-__global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
-  using G = Geo<BMAX, L, GX, GY>;
-  __shared__ uint32_t s_img[G::IMG_W];
-  __shared__ uint32_t s_h0[G::H0_W];
-  __shared__ uint32_t s_h0t[G::H0T_W];
-  __shared__ uint32_t s_meta[4][2][G::CAPW];
-  __shared__ uint32_t s_fit[4][G::CAPW];
-  __shared__ uint32_t s_mom[4][5][G::CAPW];
-  __shared__ uint32_t s_pmeta[4][G::PCAPW];
-  __shared__ uint32_t s_pm[4][G::PCAPW];
-  __shared__ unsigned long long s_mask[G::NT];
-
-  // XCD-aware order: consecutive logical blocks share an XCD (and its L2).
-  const uint32_t per = (a.n_wg + 7u) >> 3;
-  const uint32_t wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-  if (wg >= a.n_wg) return;
-  // image of this block: the number of images starting at or before it,
-  // counted with independent vector loads (no dependent search chain)
-  int lo = -1;
-  for (uint32_t k0 = 0; k0 < a.n_imgs; k0 += 64u) {
-    const uint32_t k = k0 + (threadIdx.x & 63u);
-    lo += (int)__popcll(__ballot(k < a.n_imgs && a.wg_first[k] <= wg));
-  }
-  lo = __builtin_amdgcn_readfirstlane(lo);
-  const ImgDev im = a.imgs[lo];
-  const uint32_t local = wg - im.wg_first;
-  const int gyi = (int)(local / im.groups_x), gxi = (int)(local - (uint32_t)gyi * im.groups_x);
+// Geometry of one block of top tiles and of its staged region.
+struct BlockGeo {
   Region rg;
-  rg.W = (int)im.width;
-  rg.H = (int)im.height;
-  rg.tx0 = gxi * GX;
-  rg.ty0 = gyi * GY;
-  rg.gx = min(GX, (int)im.tiles_x - rg.tx0);
-  const int gy = min(GY, (int)im.tiles_y - rg.ty0);
-  rg.tiles_x = (int)im.tiles_x;
-  rg.tile_first = im.tile_first;
-  rg.X0 = rg.tx0 * BMAX;
-  rg.Y0 = rg.ty0 * BMAX;
-  const int ntiles = rg.gx * gy;
-  const int tid = threadIdx.x;
+  const uint8_t* data;
+  uint32_t stride;
+  int gx, gy;            // tiles of the block inside the image
+  int n8, hrows;         // region: 8-pixel column groups, row pairs
+  int tx_end, ty_end;    // end of the tile block (pixels)
+};
 
-  // ---- 1. stage the tile pixels and the 2x2 mean image of the domain region
-  const int rx0 = clampi(rg.X0 - BMAX / 2, 0, rg.W - 2 * BMAX);
-  const int rx1 = clampi((rg.tx0 + rg.gx - 1) * BMAX - BMAX / 2, 0, rg.W - 2 * BMAX) + 2 * BMAX;
-  const int ry0 = clampi(rg.Y0 - BMAX / 2, 0, rg.H - 2 * BMAX);
-  const int ry1 = clampi((rg.ty0 + gy - 1) * BMAX - BMAX / 2, 0, rg.H - 2 * BMAX) + 2 * BMAX;
-  rg.ax0 = rx0 & ~7;
-  rg.ay0 = ry0 & ~7;
-  const int n8 = (rx1 - rg.ax0 + 7) >> 3;
-  const int hrows = (ry1 - rg.ay0) >> 1;
-  const int tx_end = rg.X0 + rg.gx * BMAX, ty_end = rg.Y0 + gy * BMAX;
-  uint8_t* h0t_b = reinterpret_cast<uint8_t*>(s_h0t);
-  for (int idx = tid; idx < hrows * n8; idx += 256) {
-    const int hr = idx / n8, c8 = idx - hr * n8;
-    const int x = rg.ax0 + 8 * c8, y = rg.ay0 + 2 * hr;
-    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(im.data + (size_t)y * im.stride + x);
-    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(im.data + (size_t)(y + 1) * im.stride + x);
-    uint32_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-    if (x + 8 <= rg.W) {
-      a0 = p0[0]; a1 = p0[1]; b0 = p1[0]; b1 = p1[1];
-    } else if (x < rg.W) {
-      a0 = p0[0]; b0 = p1[0];
-    }
-    // tile pixels (dword granularity: tile edges are multiples of 4)
+template <int BMAX, int GX, int GY>
+__device__ __forceinline__ BlockGeo block_geo(const BlockDesc& d) {
+  BlockGeo b;
+  b.rg.W = (int)(d.wh & 0xffffu) + 1;
+  b.rg.H = (int)(d.wh >> 16) + 1;
+  const int tx0 = (int)(d.t0 & 0xffffu), ty0 = (int)(d.t0 >> 16);
+  b.rg.tiles_x = b.rg.W / BMAX;
+  b.gx = min(GX, b.rg.tiles_x - tx0);
+  b.gy = min(GY, b.rg.H / BMAX - ty0);
+  b.rg.tg0 = d.tg0;
+  b.rg.X0 = tx0 * BMAX;
+  b.rg.Y0 = ty0 * BMAX;
+  // union of the tiles' co-centred domains (it contains every range and
+  // every descendant's domain), origin rounded down to 8 pixels
+  const int rx0 = clampi(b.rg.X0 - BMAX / 2, 0, b.rg.W - 2 * BMAX);
+  const int rx1 = clampi((tx0 + b.gx - 1) * BMAX - BMAX / 2, 0, b.rg.W - 2 * BMAX) + 2 * BMAX;
+  const int ry0 = clampi(b.rg.Y0 - BMAX / 2, 0, b.rg.H - 2 * BMAX);
+  const int ry1 = clampi((ty0 + b.gy - 1) * BMAX - BMAX / 2, 0, b.rg.H - 2 * BMAX) + 2 * BMAX;
+  b.rg.ax0 = rx0 & ~7;
+  b.rg.ay0 = ry0 & ~7;
+  b.n8 = (rx1 - b.rg.ax0 + 7) >> 3;
+  b.hrows = (ry1 - b.rg.ay0) >> 1;
+  b.tx_end = b.rg.X0 + b.gx * BMAX;
+  b.ty_end = b.rg.Y0 + b.gy * BMAX;
+  b.data = d.data;
+  b.stride = d.stride;
+  return b;
+}
+
+// Region staging.  A group is 8 x 8 pixels of the region (column group c8,
+// rows 8 g .. 8 g + 7), i.e. a 4 x 4 block of H0; lane `tid` owns groups
+// tid + 256 * it.  H0 is written as dwords, and its transpose as dwords
+// after a 4 x 4 byte transpose in registers.
+template <class G>
+struct Stage {
+  static constexpr int NC8 = G::RWA / 8;
+  static constexpr int NG = (G::HH4 / 4 * NC8 + 255) / 256;
+
+  __device__ __forceinline__ static void run(const BlockGeo& b, int tid, uint32_t* s_img, uint32_t* s_h0,
+                                             uint32_t* s_h0t) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int xx = x + 4 * h;
-      if (xx >= rg.X0 && xx < tx_end) {
-        const int col = (xx - rg.X0) >> 2;
-        if (y >= rg.Y0 && y < ty_end) s_img[(y - rg.Y0) * (G::TPITCH / 4) + col] = h ? a1 : a0;
-        if (y + 1 >= rg.Y0 && y + 1 < ty_end) s_img[(y + 1 - rg.Y0) * (G::TPITCH / 4) + col] = h ? b1 : b0;
+    for (int it = 0; it < NG; ++it) {
+      const int idx = tid + 256 * it;
+      const int g = idx / NC8, c8 = idx - g * NC8;
+      if (4 * g >= b.hrows || c8 >= b.n8) continue;
+      const int x = b.rg.ax0 + 8 * c8;
+      uint32_t v[8][2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        v[r][0] = v[r][1] = 0u;
+        const int y = b.rg.ay0 + 8 * g + r;
+        if (8 * g + r < 2 * b.hrows) {
+          const uint32_t* p = reinterpret_cast<const uint32_t*>(b.data + (size_t)y * b.stride + x);
+          if (x + 8 <= b.rg.W) {
+            v[r][0] = p[0];
+            v[r][1] = p[1];
+          } else if (x < b.rg.W) {
+            v[r][0] = p[0];
+          }
+        }
       }
+      // tile pixels (tile edges are multiples of 4 pixels)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int y = b.rg.ay0 + 8 * g + r;
+        if (y < b.rg.Y0 || y >= b.ty_end) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int xx = x + 4 * h;
+          if (xx >= b.rg.X0 && xx < b.tx_end)
+            s_img[(y - b.rg.Y0) * (G::TPITCH / 4) + ((xx - b.rg.X0) >> 2)] = v[r][h];
+        }
+      }
+      // 2x2 means: H0 rows 4g .. 4g+3, columns 4 c8 .. 4 c8 + 3
+      uint32_t hrow[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hrow[q] = mean2x2_x4(v[2 * q][0], v[2 * q][1], v[2 * q + 1][0], v[2 * q + 1][1]);
+        s_h0[(4 * g + q) * (G::HP / 4) + c8] = hrow[q];
+      }
+      // transpose the 4x4 byte block: H0T rows 4 c8 .. 4 c8 + 3, columns 4g..
+      const uint32_t u0 = __builtin_amdgcn_perm(hrow[1], hrow[0], 0x05010400u);
+      const uint32_t u1 = __builtin_amdgcn_perm(hrow[1], hrow[0], 0x07030602u);
+      const uint32_t w0 = __builtin_amdgcn_perm(hrow[3], hrow[2], 0x05010400u);
+      const uint32_t w1 = __builtin_amdgcn_perm(hrow[3], hrow[2], 0x07030602u);
+      s_h0t[(4 * c8 + 0) * (G::TP / 4) + g] = __builtin_amdgcn_perm(w0, u0, 0x05040100u);
+      s_h0t[(4 * c8 + 1) * (G::TP / 4) + g] = __builtin_amdgcn_perm(w0, u0, 0x07060302u);
+      s_h0t[(4 * c8 + 2) * (G::TP / 4) + g] = __builtin_amdgcn_perm(w1, u1, 0x05040100u);
+      s_h0t[(4 * c8 + 3) * (G::TP / 4) + g] = __builtin_amdgcn_perm(w1, u1, 0x07060302u);
     }
-    const uint32_t hv = mean2x2_x4(a0, a1, b0, b1);
-    s_h0[hr * (G::HP / 4) + c8] = hv;
-    h0t_b[(4 * c8 + 0) * G::TP + hr] = (uint8_t)hv;
-    h0t_b[(4 * c8 + 1) * G::TP + hr] = (uint8_t)(hv >> 8);
-    h0t_b[(4 * c8 + 2) * G::TP + hr] = (uint8_t)(hv >> 16);
-    h0t_b[(4 * c8 + 3) * G::TP + hr] = (uint8_t)(hv >> 24);
   }
-  for (int t = tid; t < G::NT; t += 256) s_mask[t] = 0ull;
-  __syncthreads();
+};
 
+template <int BMAX, int L, int GX, int GY>
+struct Lds {
+  using G = Geo<BMAX, L, GX, GY>;
+  uint32_t img[G::IMG_W];
+  uint32_t h0[G::H0_W];
+  uint32_t h0t[G::H0T_W];
+  uint32_t meta[4][2][G::CAPW];
+  uint32_t fit[4][G::CAPW];
+  uint32_t mom[4][5][G::CAPW];
+  uint32_t pmeta[4][G::PCAPW];
+  uint32_t pm[4][G::PCAPW];
+  unsigned long long mask[G::NT];
+};
+
+// The quadtree of one block, each wave on its own tiles.  Uses only LDS
+// data staged for the block; writes records to staging and tile masks.
+template <int BMAX, int L, int GX, int GY>
+__device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm) {
+  using G = Geo<BMAX, L, GX, GY>;
+  const Region& rg = bg.rg;
+  const int gx = bg.gx, gy = bg.gy;
+  const int tid = threadIdx.x;
+  uint32_t* s_img = sm.img;
+  uint32_t* s_h0 = sm.h0;
+  uint32_t* s_h0t = sm.h0t;
+  auto& s_meta = sm.meta;
+  auto& s_fit = sm.fit;
+  auto& s_mom = sm.mom;
+  auto& s_pmeta = sm.pmeta;
+  auto& s_pm = sm.pm;
+  unsigned long long* s_mask = sm.mask;
   // ---- 2. each wave runs the quadtree of its own tiles, independently
   const int wave = tid >> 6, lane = tid & 63;
   const int t_first = wave * G::NTW;
-  const int my_tiles = max(0, min(G::NTW, ntiles - t_first));
-  if (my_tiles == 0) return;
   uint32_t* w_meta0 = s_meta[wave][0];
   uint32_t* w_meta1 = s_meta[wave][1];
   uint32_t* w_fit = s_fit[wave];
   uint32_t* w_pmeta = s_pmeta[wave];
   uint32_t* w_pm = s_pm[wave];
-  if (lane < my_tiles) w_meta0[lane] = (uint32_t)(t_first + lane) << 16;
+  // this wave's tiles of the block that lie inside the image
+  const int my_t = t_first + lane;
+  const bool my_valid = lane < G::NTW && (my_t & (GX - 1)) < gx && (my_t >> G::LOG_GX) < gy;
+  const uint64_t vbal = __ballot(my_valid);
+  if (vbal == 0) return;   // this wave has no tile of the block inside the image
+  if (my_valid)
+    w_meta0[__builtin_amdgcn_mbcnt_hi((uint32_t)(vbal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vbal, 0u))] =
+        (uint32_t)my_t << 16;
   wave_sync();
 
-  int n = my_tiles;  // ranges in the current list (wave-uniform)
+  int n = (int)__popcll(vbal);  // ranges in the current list (wave-uniform)
   for (int lev = 1; lev <= L; ++lev) {
     uint32_t* cur = (lev & 1) ? w_meta0 : w_meta1;
     uint32_t* nxt = (lev & 1) ? w_meta1 : w_meta0;
@@ -217,7 +281,7 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
         for (int j = 0; j < 12; ++j) acc[j] = 0u;
         if (e < n) {
           int X, Y;
-          range_xy<BMAX, G::BMIN>(cur[e], rg, X, Y);
+          range_xy<BMAX, G::BMIN, G::LOG_GX>(cur[e], rg, X, Y);
           const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
           const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
           const int rx = X - rg.X0, ry = Y - rg.Y0;
@@ -240,34 +304,64 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
     if constexpr (G::BMIN <= 4) { if (B == 4) moments_fit(std::integral_constant<int, 4>{}); }
     wave_sync();
 
-    // phase 2 of the parents that failed at level lev-1 (their children are
-    // exactly the ranges just fitted, four per parent in Z order)
+    // phase 2 of the parents that failed at level lev-1: their children are
+    // exactly the ranges just fitted, four per parent in Z order, so each
+    // lane takes one child and the four lanes of a quad combine by DPP
     if (lev >= 2 && a.phase2) {
-      const int np = n >> 2;
       auto phase2 = [&](auto bconst) {
         constexpr int BB = decltype(bconst)::value;   // child side
-        for (int p = lane; p < np; p += 64) {
-          uint32_t mom[4][5];
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int s = 0; s < 5; ++s) mom[c][s] = s_mom[wave][s][4 * p + c];
-          const int m = (int)w_pm[p];
-          int O[4];
-          uint32_t bits;
-          if (fit_phase2<BB>(mom, m, lev - 1, a.thr[lev - 2], O, bits)) {
-            const uint32_t pmeta = w_pmeta[p];
-            int X, Y;
-            range_xy<BMAX, G::BMIN>(pmeta, rg, X, Y);
-            const int PB = 2 * BB;
-            const int dx = clampi(X - PB / 2, 0, rg.W - 2 * PB);
-            const int dy = clampi(Y - PB / 2, 0, rg.H - 2 * PB);
-            const int cell = morton(pmeta);
-            a.staging[tile_global(pmeta, rg) * G::CELLS + cell] =
-                make_record(X, Y, dx, dy, lev - 2, 1, 0, (int)bits, m, O[0] - m, O[1] - m, O[2] - m);
-            atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) w_fit[4 * p + c] |= kFitDead;
+        constexpr int LOGNB = 2 * Log2<BB>::value;
+        constexpr double NB = (double)(BB * BB);
+        int c1, c2, delta;
+        phase2_consts(lev - 1, c1, c2, delta);
+        const double thr2 = (400.0 * NB * NB) * (double)a.thr[lev - 2];
+        const double a1 = (double)(c1 * c1), b1 = (double)(40 * c1);
+        const double a2 = (double)(c2 * c2), b2 = (double)(40 * c2);
+        for (int base = 0; base < n; base += 64) {
+          const int e = base + lane, c = lane & 3, p = e >> 2;
+          const bool valid = e < n;
+          uint32_t sr = 0, srr = 0, sd = 0, sdd = 0, srd = 0;
+          int m = 0;
+          if (valid) {
+            sr = s_mom[wave][0][e];
+            srr = s_mom[wave][1][e];
+            sd = s_mom[wave][2][e];
+            sdd = s_mom[wave][3][e];
+            srd = s_mom[wave][4][e];
+            m = (int)w_pm[p];
+          }
+          int O = (int)((2u * sr + (uint32_t)(BB * BB)) >> (LOGNB + 1));
+          const int O0 = dpp_i<0x00>(O), O1 = dpp_i<0x55>(O), O2 = dpp_i<0xAA>(O);
+          if (c == 3) O = 4 * m - O0 - O1 - O2;                      // eq. (1)
+          const double dsr = (double)sr, dsd = (double)sd;
+          const double Q = NB * (double)sdd - dsd * dsd;
+          const double P = NB * (double)srd - dsr * dsd;
+          const double R = NB * (double)srr - dsr * dsr;
+          const double f1 = a1 * Q - b1 * P;
+          const double f2 = a2 * Q - b2 * P;
+          const bool use2 = f2 < f1;
+          const double dm = (double)O * NB - dsr;
+          const double S = (use2 ? f2 : f1) + 400.0 * R + 400.0 * (dm * dm);
+          int ok = (valid && O - m <= delta && m - O <= delta && O >= 0 && O <= 255 && S < thr2) ? 1 : 0;
+          ok &= dpp_i<0xB1>(ok);
+          ok &= dpp_i<0x4E>(ok);
+          int bits = use2 ? (1 << c) : 0;
+          bits |= dpp_i<0xB1>(bits);
+          bits |= dpp_i<0x4E>(bits);
+          if (ok) {
+            w_fit[e] |= kFitDead;
+            if (c == 0) {
+              const uint32_t pmeta = w_pmeta[p];
+              int X, Y;
+              range_xy<BMAX, G::BMIN, G::LOG_GX>(pmeta, rg, X, Y);
+              constexpr int PB = 2 * BB;
+              const int dx = clampi(X - PB / 2, 0, rg.W - 2 * PB);
+              const int dy = clampi(Y - PB / 2, 0, rg.H - 2 * PB);
+              const int cell = morton(pmeta);
+              a.staging[tile_global<G::LOG_GX>(pmeta, rg) * G::CELLS + cell] =
+                  make_record(X, Y, dx, dy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
+              atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
+            }
           }
         }
       };
@@ -290,11 +384,11 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
         if (!(fit & kFitDead)) {
           if (fit & kFitAccept) {
             int X, Y;
-            range_xy<BMAX, G::BMIN>(meta, rg, X, Y);
+            range_xy<BMAX, G::BMIN, G::LOG_GX>(meta, rg, X, Y);
             const int dx = clampi(X - B / 2, 0, rg.W - 2 * B);
             const int dy = clampi(Y - B / 2, 0, rg.H - 2 * B);
             const int cell = morton(meta);
-            a.staging[tile_global(meta, rg) * G::CELLS + cell] =
+            a.staging[tile_global<G::LOG_GX>(meta, rg) * G::CELLS + cell] =
                 make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                             (int)(fit & 0xffu), 0, 0, 0);
             atomicOr(&s_mask[meta >> 16], 1ull << cell);
@@ -324,10 +418,48 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
 
   // ---- publish the wave's tiles' occupancy masks
   wave_sync();
-  if (lane < my_tiles) {
-    const uint32_t meta = (uint32_t)(t_first + lane) << 16;
-    a.masks[tile_global(meta, rg)] = s_mask[t_first + lane];
+  if (my_valid) a.masks[tile_global<G::LOG_GX>((uint32_t)my_t << 16, rg)] = s_mask[my_t];
+}
+
+template <int BMAX, int L, int GX, int GY>
+__global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
+  using G = Geo<BMAX, L, GX, GY>;
+  __shared__ Lds<BMAX, L, GX, GY> sm;
+  const int tid = threadIdx.x;
+  // XCD-aware order: consecutive logical blocks share an XCD (and its L2).
+  const uint32_t per = (a.n_wg + 7u) >> 3;
+  const uint32_t wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (wg >= a.n_wg) return;
+  const BlockGeo bg = block_geo<BMAX, GX, GY>(a.blocks[wg]);
+  Stage<G>::run(bg, tid, sm.img, sm.h0, sm.h0t);
+  for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
+  __syncthreads();
+  process_block<BMAX, L, GX, GY>(a, bg, sm);
+}
+
+// One lane per logical workgroup: find its image (binary search over the
+// sorted first-workgroup indices) and its block of tiles.
+__global__ __launch_bounds__(256) void block_prep_kernel(const ImgDev* imgs, uint32_t n_imgs, uint32_t n_wg,
+                                                        int b_max, int gx, int gy, BlockDesc* blocks) {
+  const uint32_t wg = blockIdx.x * 256u + threadIdx.x;
+  if (wg >= n_wg) return;
+  int lo = 0, hi = (int)n_imgs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (imgs[mid].wg_first <= wg) lo = mid; else hi = mid - 1;
   }
+  const ImgDev im = imgs[lo];
+  const uint32_t local = wg - im.wg_first;
+  const uint32_t gyi = local / im.groups_x, gxi = local - gyi * im.groups_x;
+  const uint32_t tx0 = gxi * (uint32_t)gx, ty0 = gyi * (uint32_t)gy;
+  BlockDesc d;
+  d.data = im.data;
+  d.tg0 = im.tile_first + (uint64_t)ty0 * im.tiles_x + tx0;
+  d.stride = im.stride;
+  d.wh = (im.width - 1u) | ((im.height - 1u) << 16);
+  d.t0 = tx0 | (ty0 << 16);
+  d.pad = 0;
+  blocks[wg] = d;
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, size_t n) {
@@ -464,13 +596,14 @@ static hipError_t launch_one(const EncodeArgs& a, hipStream_t s) {
 
 // Tile shapes (GX x GY top tiles per workgroup) instantiated per
 // (b_max, levels); the first entry is the default.
-#define FE_SHAPES(X)                                                     \
-  X(4, 1, 16, 16) X(4, 1, 32, 8)                                         \
-  X(8, 1, 16, 8) X(8, 1, 8, 8) X(8, 2, 8, 8) X(8, 2, 16, 4) X(8, 2, 4, 4) \
-  X(16, 1, 8, 4) X(16, 1, 4, 4) X(16, 2, 8, 4) X(16, 2, 4, 4)            \
-  X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2) X(16, 3, 8, 2)           \
-  X(32, 1, 4, 2) X(32, 2, 4, 2) X(32, 3, 4, 2) X(32, 3, 2, 2)            \
-  X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1)
+#define FE_SHAPES(X)                                                                    \
+  X(4, 1, 16, 16) X(4, 1, 32, 8)                                                        \
+  X(8, 1, 16, 8) X(8, 1, 8, 8) X(8, 2, 8, 8) X(8, 2, 16, 4) X(8, 2, 4, 4) X(8, 2, 8, 4)  \
+  X(16, 1, 8, 4) X(16, 1, 4, 4) X(16, 2, 8, 4) X(16, 2, 4, 4) X(16, 2, 8, 2)             \
+  X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2) X(16, 3, 8, 2) X(16, 3, 4, 2)            \
+  X(16, 3, 16, 4)                                                                       \
+  X(32, 1, 4, 2) X(32, 1, 2, 2) X(32, 2, 4, 2) X(32, 2, 2, 2) X(32, 3, 4, 2)             \
+  X(32, 3, 2, 2) X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1) X(32, 4, 4, 1)
 
 int encode_shapes(int b_max, int levels, TileShape* out, int max_out) {
   int k = 0;
@@ -487,6 +620,14 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
   FE_SHAPES(FE_LAUNCH)
 #undef FE_LAUNCH
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_block_prep(const ImgDev* imgs, uint32_t n_imgs, uint32_t n_wg, int b_max, int gx, int gy,
+                             BlockDesc* blocks, hipStream_t s) {
+  if (n_wg == 0) return hipSuccess;
+  hipLaunchKernelGGL(block_prep_kernel, dim3((n_wg + 255) / 256), dim3(256), 0, s, imgs, n_imgs, n_wg, b_max, gx,
+                     gy, blocks);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
