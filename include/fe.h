@@ -246,6 +246,22 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
                     uint8_t* d_out, void* stream);
 
 /*
+ * Exhaustive search of explicit ranges (Sec. 1): for each range of side
+ * `block` (4, 8 or 16) at d_xy[i] (x | y << 16, multiples of block), find
+ * the best of all (W - 2B + 1)(H - 2B + 1) step-1 domains, 8 isometries and
+ * contrasts k/8 (minimum S, then lowest domain index v * (W - 2B + 1) + u,
+ * then lowest isometry, then lowest k).  Writes 4 uint32 per range:
+ * domain index, e | k << 8 | m << 16, and S as low / high 32-bit words.
+ * The image must satisfy fe_validate for b_max = block, and the number of
+ * domain origins must be below 2^20 (FE_ERR_SHAPE otherwise).  fe_encode
+ * with FE_FULL_SEARCH runs the same search inside the quadtree (b_max <=
+ * 16); its records hold the chosen domain origin in dx, dy.
+ */
+fe_status fe_full_search_ranges(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t height,
+                                uint32_t stride, uint32_t block, const uint32_t* d_xy, uint32_t count,
+                                uint32_t* d_out, void* stream);
+
+/*
  * Tile shapes of the fused encode kernel.  A workgroup runs the quadtrees of
  * a gx x gy block of top-level tiles (b_max x b_max each); the shape trades
  * LDS per workgroup (occupancy) against the halo of domain pixels staged

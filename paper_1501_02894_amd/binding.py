@@ -71,6 +71,7 @@ _SIGNATURES = {
     "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
+    "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_tile_shapes": (ctypes.c_int, [_U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.c_int]),
     "fe_set_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, _U32, _U32]),
     "fe_get_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
@@ -231,6 +232,19 @@ def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: 
     return out
 
 
+def fe_full_search_ranges(ctx: int, img, block: int, xy, out=None, stream=None):
+    """Exhaustive best match of explicit ranges; returns an (n, 4) int32
+    tensor: domain index, e | k << 8 | m << 16, S low, S high."""
+    import torch
+    H, W = img.shape
+    count = int(xy.numel())
+    if out is None:
+        out = torch.zeros((count, 4), dtype=torch.int32, device=img.device)
+    _check(load().fe_full_search_ranges(ctx, _ptr(img), W, H, img.stride(0), int(block), _ptr(xy), count,
+                                        _ptr(out), _stream(stream)))
+    return out
+
+
 def fe_tile_shapes(b_max: int, b_min: int):
     gx = (_U32 * 16)()
     gy = (_U32 * 16)()
@@ -320,6 +334,9 @@ class Context:
 
     def encode_batch(self, imgs, b_max, b_min, thresholds, phase2=True, **kw):
         return fe_encode_batch(self.handle, imgs, make_params(b_max, b_min, thresholds, phase2), **kw)
+
+    def full_search_ranges(self, img, block, xy, **kw):
+        return fe_full_search_ranges(self.handle, img, block, xy, **kw)
 
     def decode(self, transforms, width, height, b_max, iters, start=None, **kw):
         return fe_decode(self.handle, transforms, width, height, b_max, iters, start=start, **kw)

@@ -28,6 +28,25 @@ struct fe_ctx {
   size_t chunk_base_n = 0;
   fe::BlockDesc* blocks = nullptr;
   size_t blocks_n = 0;
+  // exhaustive search scratch
+  uint8_t* fs_planes = nullptr;
+  size_t fs_planes_n = 0;
+  uint32_t* fs_sd = nullptr;
+  size_t fs_sd_n = 0;
+  double* fs_qd = nullptr;
+  size_t fs_qd_n = 0;
+  uint32_t* fs_xy[2] = {nullptr, nullptr};
+  size_t fs_xy_n[2] = {0, 0};
+  uint8_t* fs_frag = nullptr;
+  size_t fs_frag_n = 0;
+  uint32_t* fs_sr = nullptr;
+  size_t fs_sr_n = 0;
+  double* fs_alpha = nullptr;
+  size_t fs_alpha_n = 0;
+  double* fs_beta = nullptr;
+  size_t fs_beta_n = 0;
+  uint64_t* fs_best = nullptr;
+  size_t fs_best_n = 0;
   uint64_t* offsets = nullptr;
   size_t offsets_n = 0;
   uint32_t* flags = nullptr;          // small device counters
@@ -209,6 +228,99 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   return FE_OK;
 }
 
+// Scratch for the exhaustive search of up to R ranges of side B.
+fe_status fs_reserve(fe_ctx* ctx, const fe::FsPlan& pl, uint32_t R) {
+  fe_status st;
+  if ((st = ensure(ctx->fs_sd, ctx->fs_sd_n, (size_t)pl.ndom, "domain sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_qd, ctx->fs_qd_n, (size_t)pl.ndom, "domain Q")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_frag, ctx->fs_frag_n, fe::fs_frag_bytes(pl.B, R), "A fragments")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_sr, ctx->fs_sr_n, (size_t)R, "range sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_alpha, ctx->fs_alpha_n, (size_t)R, "range alpha")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_beta, ctx->fs_beta_n, (size_t)R, "range beta")) != FE_OK) return st;
+  if ((st = ensure(ctx->fs_best, ctx->fs_best_n, (size_t)R, "best keys")) != FE_OK) return st;
+  return FE_OK;
+}
+
+fe_status fs_check(uint32_t w, uint32_t h, uint32_t b_max, uint32_t b_min) {
+  if (b_max > 16) return fe::fail(FE_ERR_INVALID, "exhaustive search supports b_max <= 16");
+  const fe::FsPlan pl = fe::fs_plan(w, h, b_min);
+  if (pl.ndom >= fe::kFsMaxDomains)
+    return fe::fail(FE_ERR_SHAPE, "exhaustive search: %llu domain origins exceed the limit of %llu",
+                    (unsigned long long)pl.ndom, (unsigned long long)fe::kFsMaxDomains);
+  return FE_OK;
+}
+
+// Exhaustive-search quadtree of one image: per level, MFMA search of every
+// listed range, exact finalisation, children queued on the device; the
+// host reads each level's child count.
+fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride,
+                             const fe_params* p, fe_transform* d_out, size_t cap, size_t* n_out, hipStream_t s) {
+  fe_status st = fs_check(w, h, p->b_max, p->b_min);
+  if (st != FE_OK) return st;
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  const int cells = 1 << (2 * (L - 1));
+  const uint64_t tiles = (uint64_t)(w / p->b_max) * (h / p->b_max);
+  const size_t max_ranges = (size_t)tiles * cells;
+  const fe::FsPlan pl0 = fe::fs_plan(w, h, p->b_max);
+  if ((st = ensure(ctx->fs_planes, ctx->fs_planes_n, pl0.plane_bytes, "phase planes")) != FE_OK) return st;
+  for (int b = 0; b < 2; ++b)
+    if ((st = ensure(ctx->fs_xy[b], ctx->fs_xy_n[b], max_ranges, "range lists")) != FE_OK) return st;
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
+  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
+  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
+  if ((st = ensure(ctx->offsets, ctx->offsets_n, 2, "offsets")) != FE_OK) return st;
+  fe::ImgDev im{};
+  im.data = d_img;
+  im.width = w;
+  im.height = h;
+  im.stride = stride;
+  im.tiles_x = w / p->b_max;
+  im.tiles_y = h / p->b_max;
+  im.groups_x = im.tiles_x;
+  im.groups_y = im.tiles_y;
+  im.wg_first = 0;
+  im.tile_first = 0;
+  if ((st = upload_table(ctx, &im, 1, s)) != FE_OK) return st;
+  FE_HIP(fe::launch_zero_u32(reinterpret_cast<uint32_t*>(ctx->masks), (size_t)tiles * 2, s), "zero masks");
+  FE_HIP(fe::fs_planes(pl0, d_img, w, h, stride, ctx->fs_planes, s), "phase planes");
+  FE_HIP(fe::fs_level1(w, h, p->b_max, ctx->fs_xy[0], s), "level-1 ranges");
+  uint32_t R = (uint32_t)tiles;
+  for (int lev = 1; lev <= L && R > 0; ++lev) {
+    const uint32_t B = p->b_max >> (lev - 1);
+    const fe::FsPlan pl = fe::fs_plan(w, h, B);
+    if ((st = fs_reserve(ctx, pl, R)) != FE_OK) return st;
+    const uint32_t* xy = ctx->fs_xy[(lev - 1) & 1];
+    uint32_t* nxt = ctx->fs_xy[lev & 1];
+    FE_HIP(fe::fs_domain_sums(pl, w, h, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, s), "domain sums");
+    {
+      Timed t(ctx, FE_TIMING_FULLSEARCH, s);
+      FE_HIP(fe::fs_search(pl, d_img, w, h, stride, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, xy, R, ctx->fs_frag,
+                           ctx->fs_sr, ctx->fs_alpha, ctx->fs_beta, ctx->fs_best, s),
+             "search launch");
+    }
+    FE_HIP(fe::launch_zero_u32(ctx->flags, 1, s), "zero count");
+    const bool last = lev == L;
+    FE_HIP(fe::fs_finalize(pl, d_img, w, h, stride, ctx->fs_planes, xy, R, ctx->fs_best, lev, last ? 1 : 0,
+                           last ? 0u : p->mse_thr[lev - 1], p->b_max, p->b_min, ctx->staging, ctx->masks, nxt,
+                           ctx->flags, s),
+           "finalize launch");
+    if (last) break;
+    FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count");
+    FE_HIP(hipStreamSynchronize(s), "level");
+    R = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
+  }
+  FE_HIP(fe::launch_scatter(ctx->d_table, 1, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->chunk_base, ctx->staging,
+                            reinterpret_cast<uint4*>(d_out), (uint64_t)cap, ctx->offsets, s),
+         "scatter launch");
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->offsets + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "count");
+  FE_HIP(hipStreamSynchronize(s), "encode");
+  *n_out = (size_t)ctx->h_scalars[0];
+  if (*n_out > cap) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
+  return FE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -252,6 +364,16 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->chunk_sum);
   (void)hipFree(c->chunk_base);
   (void)hipFree(c->blocks);
+  (void)hipFree(c->fs_planes);
+  (void)hipFree(c->fs_sd);
+  (void)hipFree(c->fs_qd);
+  (void)hipFree(c->fs_xy[0]);
+  (void)hipFree(c->fs_xy[1]);
+  (void)hipFree(c->fs_frag);
+  (void)hipFree(c->fs_sr);
+  (void)hipFree(c->fs_alpha);
+  (void)hipFree(c->fs_beta);
+  (void)hipFree(c->fs_best);
   (void)hipFree(c->offsets);
   (void)hipFree(c->flags);
   (void)hipFree(c->tmp_img);
@@ -298,8 +420,8 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, u
   if (st != FE_OK) return st;
   if ((uintptr_t)d_img & 3) return fe::fail(FE_ERR_SHAPE, "image must be 4-byte aligned");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
-  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "exhaustive search is not available");
   DeviceGuard g(ctx->device);
+  if (p->flags & FE_FULL_SEARCH) return encode_full_search(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
   fe_image_desc one{d_img, w, h, stride, 0};
   return encode_images(ctx, &one, 1, p, d_out, cap, nullptr, n_out, (hipStream_t)stream);
 }
@@ -433,6 +555,32 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
   *gx = (uint32_t)best_shape.gx;
   *gy = (uint32_t)best_shape.gy;
   *ms = best;
+  return FE_OK;
+}
+
+fe_status fe_full_search_ranges(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride,
+                                uint32_t block, const uint32_t* d_xy, uint32_t count, uint32_t* d_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_img || (count && (!d_xy || !d_out))) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (block != 4 && block != 8 && block != 16) return fe::fail(FE_ERR_INVALID, "block must be 4, 8 or 16");
+  fe_status st = fe::check_shape(w, h, stride, block);
+  if (st != FE_OK) return st;
+  if ((st = fs_check(w, h, block, block)) != FE_OK) return st;
+  if (count == 0) return FE_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const fe::FsPlan pl = fe::fs_plan(w, h, block);
+  if ((st = ensure(ctx->fs_planes, ctx->fs_planes_n, pl.plane_bytes, "phase planes")) != FE_OK) return st;
+  if ((st = fs_reserve(ctx, pl, count)) != FE_OK) return st;
+  FE_HIP(fe::fs_planes(pl, d_img, w, h, stride, ctx->fs_planes, s), "phase planes");
+  FE_HIP(fe::fs_domain_sums(pl, w, h, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, s), "domain sums");
+  {
+    Timed t(ctx, FE_TIMING_FULLSEARCH, s);
+    FE_HIP(fe::fs_search(pl, d_img, w, h, stride, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, d_xy, count, ctx->fs_frag,
+                         ctx->fs_sr, ctx->fs_alpha, ctx->fs_beta, ctx->fs_best, s),
+           "search launch");
+  }
+  FE_HIP(fe::fs_report(pl, d_img, w, h, stride, ctx->fs_planes, d_xy, count, ctx->fs_best, d_out, s), "report");
   return FE_OK;
 }
 

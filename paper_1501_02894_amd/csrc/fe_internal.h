@@ -93,4 +93,33 @@ hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint
 hipError_t launch_decode_iter(const DecodeArgs& a, const uint8_t* cur, uint8_t* nxt,
                               hipStream_t stream);
 
+// Exhaustive search (one image).  Plans, the 2x2 phase planes, per-level
+// domain sums, the MFMA search of a list of ranges (best key per range),
+// and the per-range finalisation into records / next-level ranges.
+struct FsPlan {
+  uint32_t B, nu, nv;      // block side; domain origins per row / column
+  uint32_t pitch, prow;    // phase-plane pitch (bytes) and rows
+  size_t plane_bytes;      // all four planes
+  uint64_t ndom;           // nu * nv
+};
+constexpr uint64_t kFsMaxDomains = 1u << 20;   // domain index must fit the 64-bit best key
+
+FsPlan fs_plan(uint32_t w, uint32_t h, uint32_t B);
+size_t fs_frag_bytes(uint32_t B, uint32_t R);
+hipError_t fs_planes(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                     uint8_t* planes, hipStream_t s);
+hipError_t fs_domain_sums(const FsPlan& pl, uint32_t w, uint32_t h, const uint8_t* planes, uint32_t* sd,
+                          double* qd, hipStream_t s);
+hipError_t fs_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                     const uint8_t* planes, const uint32_t* sd, const double* qd, const uint32_t* xy, uint32_t R,
+                     uint8_t* frag, uint32_t* sr, double* alpha, double* beta, uint64_t* best, hipStream_t s);
+hipError_t fs_finalize(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                       const uint8_t* planes, const uint32_t* xy, uint32_t R, const uint64_t* best, int level,
+                       int last, uint32_t thr, uint32_t b_max, uint32_t b_min, uint4* staging, uint64_t* masks,
+                       uint32_t* next_xy, uint32_t* next_count, hipStream_t s);
+hipError_t fs_report(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                     const uint8_t* planes, const uint32_t* xy, uint32_t R, const uint64_t* best, uint32_t* out,
+                     hipStream_t s);
+hipError_t fs_level1(uint32_t w, uint32_t h, uint32_t b_max, uint32_t* xy, hipStream_t s);
+
 }  // namespace fe
