@@ -287,6 +287,48 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
                       uint32_t* gy, double* ms, void* stream);
 
 /*
+ * Encode server (continuous batching).  One parameter set per server.
+ *
+ * fe_server_create: device memory of `hbm_budget` bytes (a quarter holds
+ * per-tile record slots and masks, the rest images, outputs and ordering
+ * scratch) and `host_budget` bytes of pinned host memory for inputs and
+ * results are reserved up front; at most `max_slots` requests are admitted
+ * at once; one step launches the fused kernel over at most `step_blocks`
+ * workgroup blocks of top tiles drawn first-come first-served from all
+ * admitted requests.  A worker thread drives the steps.
+ *
+ * fe_server_submit copies the host image (W x H, row pitch `stride`) into
+ * pinned staging and queues it; the caller may reuse h_img on return.
+ * FE_ERR_BUSY when the pinned staging is full (retry later), FE_ERR_OOM
+ * when the request can never fit the device budget, FE_ERR_SHAPE /
+ * FE_ERR_INVALID as fe_validate.  Requests are admitted in arrival order
+ * when their device footprint fits.
+ *
+ * fe_server_poll: *done = 0 while the request runs.  When done, *n is the
+ * stream length and *latency_ms the time from submit to the records being
+ * in host memory; if h_out is not NULL the stream is copied there (cap >=
+ * *n, else FE_ERR_CAPACITY and nothing is released) and the request is
+ * released (its id becomes unknown).  A request that failed on the device
+ * returns FE_ERR_DEVICE and is released.  The stream equals fe_encode's for
+ * the same image and parameters, whatever else was in flight.
+ *
+ * fe_server_destroy stops the worker, waits for the device and frees
+ * everything, including unfetched results.  Submit / poll / stats may be
+ * called from several threads.
+ */
+typedef struct fe_server fe_server;
+
+fe_status fe_server_create(int device, const fe_params* params, size_t hbm_budget, size_t host_budget,
+                           uint32_t max_slots, uint32_t step_blocks, fe_server** out);
+fe_status fe_server_submit(fe_server* server, const uint8_t* h_img, uint32_t width, uint32_t height,
+                           uint32_t stride, uint64_t* req);
+fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, size_t cap, size_t* n,
+                         int* done, double* latency_ms);
+fe_status fe_server_stats(fe_server* server, uint64_t* steps, uint64_t* blocks, uint64_t* completed,
+                          size_t* hbm_used, uint32_t* in_flight, uint32_t* queued);
+void fe_server_destroy(fe_server* server);
+
+/*
  * Kernel timing.  While enabled, each launch of the library's main kernels
  * (below) is bracketed by HIP events recorded on the launch's own stream.
  * fe_timing_read waits for those events, adds each kernel's event-to-event

@@ -72,6 +72,15 @@ _SIGNATURES = {
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
     "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
+    "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
+                                        ctypes.POINTER(_VP)]),
+    "fe_server_submit": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _SZ, ctypes.POINTER(_SZ), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "fe_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_SZ), ctypes.POINTER(_U32),
+                                       ctypes.POINTER(_U32)]),
+    "fe_server_destroy": (None, [_VP]),
     "fe_tile_shapes": (ctypes.c_int, [_U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.c_int]),
     "fe_set_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, _U32, _U32]),
     "fe_get_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
@@ -297,6 +306,82 @@ def to_records(t) -> np.ndarray:
     """Device (n, 16) uint8 tensor -> host structured array."""
     a = t.detach().cpu().numpy()
     return np.ascontiguousarray(a).view(TRANSFORM_DTYPE).reshape(-1)
+
+
+def fe_server_create(device: int, params: fe_params, hbm_budget: int, host_budget: int, max_slots: int,
+                     step_blocks: int) -> int:
+    h = _VP()
+    _check(load().fe_server_create(device, ctypes.byref(params), hbm_budget, host_budget, max_slots, step_blocks,
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def fe_server_submit(server: int, img: np.ndarray) -> int:
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    req = ctypes.c_uint64(0)
+    _check(load().fe_server_submit(server, img.ctypes.data, W, H, W, ctypes.byref(req)))
+    return req.value
+
+
+def fe_server_poll(server: int, req: int, fetch: bool = True):
+    """Returns (done, records or None, latency_ms)."""
+    lib = load()
+    n = _SZ(0)
+    done = ctypes.c_int(0)
+    lat = ctypes.c_double(0)
+    _check(lib.fe_server_poll(server, req, None, 0, ctypes.byref(n), ctypes.byref(done), ctypes.byref(lat)))
+    if not done.value:
+        return False, None, None
+    if not fetch:
+        return True, None, lat.value
+    out = np.empty(max(n.value, 1), TRANSFORM_DTYPE)
+    _check(lib.fe_server_poll(server, req, out.ctypes.data, out.size, ctypes.byref(n), ctypes.byref(done),
+                              ctypes.byref(lat)))
+    return True, out[: n.value], lat.value
+
+
+def fe_server_stats(server: int) -> dict:
+    v = [ctypes.c_uint64(0) for _ in range(3)]
+    used = _SZ(0)
+    fl, q = _U32(0), _U32(0)
+    _check(load().fe_server_stats(server, ctypes.byref(v[0]), ctypes.byref(v[1]), ctypes.byref(v[2]),
+                                  ctypes.byref(used), ctypes.byref(fl), ctypes.byref(q)))
+    return {"steps": v[0].value, "blocks": v[1].value, "completed": v[2].value, "hbm_used": used.value,
+            "in_flight": fl.value, "queued": q.value}
+
+
+def fe_server_destroy(server: int) -> None:
+    load().fe_server_destroy(server)
+
+
+class Server:
+    """Continuous-batching encode server (one parameter set)."""
+
+    def __init__(self, b_max, b_min, thresholds, phase2=True, device=0, hbm_budget=8 << 30,
+                 host_budget=2 << 30, max_slots=256, step_blocks=4096):
+        self.handle = fe_server_create(device, make_params(b_max, b_min, thresholds, phase2), hbm_budget,
+                                       host_budget, max_slots, step_blocks)
+
+    def submit(self, img):
+        return fe_server_submit(self.handle, img)
+
+    def poll(self, req, fetch=True):
+        return fe_server_poll(self.handle, req, fetch)
+
+    def stats(self):
+        return fe_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            fe_server_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Context:

@@ -1,0 +1,540 @@
+// Continuous-batching encode server.
+//
+// Requests (host images, one parameter set per server) are queued by
+// fe_server_submit.  A worker thread runs steps:
+//   1. admission: queued requests enter in arrival order while a slot is
+//      free and their device footprint fits: image, output, per-request
+//      ordering scratch (byte arena) and their top tiles' record slots and
+//      occupancy masks (tile arena).  The image is copied to the device on a
+//      copy stream and the masks are cleared there;
+//   2. one launch of the fused MNS kernel over up to `step_blocks` blocks of
+//      top tiles taken first-come first-served from every admitted request
+//      whose image has arrived: mixed image sizes share the launch, and a
+//      large image is spread over several steps;
+//   3. a request whose last block has run gets its stream ordered on the
+//      device and its record count copied back; when the count arrives, the
+//      records themselves are copied back (exactly that many) and the
+//      request completes.
+// Records of a request live in its own tile slots, so they do not depend on
+// what else shares the steps.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "fe.h"
+#include "fe_common.h"
+#include "fe_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) in units of `granule` (host-side
+// bookkeeping of a device or pinned host allocation, or of tile slots).
+class Arena {
+ public:
+  void reset(size_t size, size_t granule) {
+    free_.clear();
+    g_ = granule;
+    size_ = size / g_ * g_;
+    used_ = 0;
+    if (size_) free_[0] = size_;
+  }
+  size_t round(size_t n) const { return (n + g_ - 1) / g_ * g_; }
+  // offset, or SIZE_MAX when no free run is long enough
+  size_t alloc(size_t n) {
+    n = round(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        used_ += n;
+        return off;
+      }
+    }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t n) {
+    n = round(n);
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0, used_ = 0, g_ = 1;
+};
+
+enum class ReqState { Queued, Copying, Running, Counting, Fetching, Done, Failed };
+
+struct Request {
+  uint64_t id = 0;
+  uint32_t w = 0, h = 0, pitch = 0;
+  uint32_t tiles_x = 0, tiles_y = 0, groups_x = 0;
+  uint64_t tiles = 0, blocks = 0, next_block = 0;
+  size_t cap = 0;                        // device output capacity (transforms)
+  size_t chunks = 0;
+  size_t hin_off = 0, hin_len = 0;       // pinned host input copy
+  size_t dev_off = 0, dev_len = 0;       // byte arena region
+  size_t img_off = 0, out_off = 0, ofs_off = 0, csum_off = 0, cbase_off = 0;
+  size_t tile_base = 0, tile_len = 0;    // tile arena range
+  size_t hout_off = 0, hout_len = 0;     // pinned host output
+  int slot = -1;                         // pinned count slot
+  hipEvent_t ev_copied = nullptr, ev_counted = nullptr, ev_fetched = nullptr;
+  ReqState state = ReqState::Queued;
+  size_t n_out = 0;
+  Clock::time_point t_submit, t_done;
+  fe_status error = FE_OK;
+};
+
+}  // namespace
+
+struct fe_server {
+  int device = 0;
+  fe_params params{};
+  int L = 0, cells = 0;
+  fe::TileShape shape{};
+  hipStream_t compute = nullptr, copy = nullptr;
+  uint8_t* dev_base = nullptr;           // byte arena memory
+  uint4* staging = nullptr;              // tile arena: record slots
+  uint64_t* masks = nullptr;             // tile arena: occupancy
+  uint8_t* host_base = nullptr;          // pinned host arena
+  uint64_t* h_counts = nullptr;          // pinned: one record count per slot
+  Arena dev_arena, tile_arena, host_arena;
+  std::vector<int> free_slots;
+  uint32_t max_slots = 0, step_blocks = 0;
+  fe::ImgDev* d_one = nullptr;           // one-image table (tile_first 0) for ordering
+  fe::BlockDesc* h_desc[2] = {nullptr, nullptr};
+  fe::BlockDesc* d_desc[2] = {nullptr, nullptr};
+  hipEvent_t step_done[2] = {nullptr, nullptr};
+  int step_slot = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queued;
+  std::vector<Request*> active;          // admitted, not yet done
+  std::map<uint64_t, Request*> all;      // by id, until fetched
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  uint64_t steps = 0, blocks_run = 0, completed = 0;
+};
+
+namespace {
+
+size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Device byte footprint of a request (image, output, offsets, ordering
+// scratch); its tile slots are accounted in the tile arena.
+size_t byte_footprint(const Request* r) {
+  return r256((size_t)r->pitch * r->h) + r256(r->cap * 16) + 256 + r256(r->chunks * 4) + r256((r->chunks + 1) * 8);
+}
+
+void release_request(fe_server* s, Request* r) {
+  if (r->dev_len) s->dev_arena.release(r->dev_off, r->dev_len);
+  if (r->tile_len) s->tile_arena.release(r->tile_base, r->tile_len);
+  if (r->hin_len) s->host_arena.release(r->hin_off, r->hin_len);
+  if (r->hout_len) s->host_arena.release(r->hout_off, r->hout_len);
+  if (r->slot >= 0) s->free_slots.push_back(r->slot);
+  r->dev_len = r->tile_len = r->hin_len = r->hout_len = 0;
+  r->slot = -1;
+  for (hipEvent_t* e : {&r->ev_copied, &r->ev_counted, &r->ev_fetched})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+}
+
+void fail_request(Request* r) {
+  r->state = ReqState::Failed;
+  r->error = FE_ERR_DEVICE;
+}
+
+// Admit queued requests in arrival order while slots and memory allow.
+// Lock held.
+bool admit(fe_server* s) {
+  bool any = false;
+  while (!s->queued.empty() && !s->free_slots.empty()) {
+    Request* r = s->queued.front();
+    const size_t need = byte_footprint(r);
+    const size_t off = s->dev_arena.alloc(need);
+    if (off == SIZE_MAX) break;   // head of the queue waits for memory
+    const size_t tb = s->tile_arena.alloc(r->tiles);
+    if (tb == SIZE_MAX) {
+      s->dev_arena.release(off, need);
+      break;
+    }
+    s->queued.pop_front();
+    any = true;
+    r->dev_off = off;
+    r->dev_len = need;
+    r->img_off = off;
+    r->out_off = r->img_off + r256((size_t)r->pitch * r->h);
+    r->ofs_off = r->out_off + r256(r->cap * 16);
+    r->csum_off = r->ofs_off + 256;
+    r->cbase_off = r->csum_off + r256(r->chunks * 4);
+    r->tile_base = tb;
+    r->tile_len = r->tiles;
+    r->slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    hipError_t e = hipEventCreateWithFlags(&r->ev_copied, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_counted, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_fetched, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
+                         hipMemcpyHostToDevice, s->copy);
+    if (e == hipSuccess)
+      e = fe::launch_zero_u32(reinterpret_cast<uint32_t*>(s->masks + r->tile_base), (size_t)r->tiles * 2, s->copy);
+    if (e == hipSuccess) e = hipEventRecord(r->ev_copied, s->copy);
+    if (e != hipSuccess) {
+      fail_request(r);
+    } else {
+      r->state = ReqState::Copying;
+    }
+    s->active.push_back(r);
+  }
+  return any;
+}
+
+// One step: a single launch over up to step_blocks blocks.  Returns true if
+// it launched work.  Lock held on entry and exit.
+bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
+  std::vector<Request*> ready;
+  for (Request* r : s->active) {
+    if (r->state == ReqState::Copying && hipEventQuery(r->ev_copied) == hipSuccess) r->state = ReqState::Running;
+    if (r->state == ReqState::Running && r->next_block < r->blocks) ready.push_back(r);
+  }
+  if (ready.empty()) return false;
+  const int slot = s->step_slot;
+  s->step_slot ^= 1;
+  lk.unlock();
+  (void)hipEventSynchronize(s->step_done[slot]);   // its descriptor buffer is free again
+  lk.lock();
+  fe::BlockDesc* hd = s->h_desc[slot];
+  uint32_t n = 0;
+  std::vector<Request*> finishing;
+  for (Request* r : ready) {
+    if (n >= s->step_blocks) break;
+    while (r->next_block < r->blocks && n < s->step_blocks) {
+      const uint64_t b = r->next_block++;
+      const uint32_t gyi = (uint32_t)(b / r->groups_x), gxi = (uint32_t)(b - (uint64_t)gyi * r->groups_x);
+      const uint32_t tx0 = gxi * (uint32_t)s->shape.gx, ty0 = gyi * (uint32_t)s->shape.gy;
+      fe::BlockDesc& d = hd[n++];
+      d.data = s->dev_base + r->img_off;
+      d.tg0 = r->tile_base + (uint64_t)ty0 * r->tiles_x + tx0;
+      d.stride = r->pitch;
+      d.wh = (r->w - 1u) | ((r->h - 1u) << 16);
+      d.t0 = tx0 | (ty0 << 16);
+      d.pad = 0;
+    }
+    if (r->next_block == r->blocks) finishing.push_back(r);
+  }
+  lk.unlock();
+  hipError_t e = hipMemcpyAsync(s->d_desc[slot], hd, (size_t)n * sizeof(fe::BlockDesc), hipMemcpyHostToDevice,
+                                s->compute);
+  if (e == hipSuccess) {
+    fe::EncodeArgs a{};
+    a.blocks = s->d_desc[slot];
+    a.n_imgs = 1;
+    a.n_wg = n;
+    a.phase2 = (s->params.flags & FE_PHASE2) ? 1u : 0u;
+    for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)s->params.n_thr ? s->params.mse_thr[l] : 0u;
+    a.staging = s->staging;
+    a.masks = s->masks;
+    e = fe::launch_mns_tiles((int)s->params.b_max, s->L, s->shape, a, s->compute);
+  }
+  for (Request* r : finishing) {
+    if (e != hipSuccess) break;
+    e = fe::launch_scatter(s->d_one, 1, r->tiles, s->cells, s->masks + r->tile_base,
+                           reinterpret_cast<uint32_t*>(s->dev_base + r->csum_off),
+                           reinterpret_cast<uint64_t*>(s->dev_base + r->cbase_off),
+                           s->staging + r->tile_base * (size_t)s->cells,
+                           reinterpret_cast<uint4*>(s->dev_base + r->out_off), r->cap,
+                           reinterpret_cast<uint64_t*>(s->dev_base + r->ofs_off), s->compute);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&s->h_counts[r->slot], s->dev_base + r->ofs_off + 8, 8, hipMemcpyDeviceToHost, s->compute);
+    if (e == hipSuccess) e = hipEventRecord(r->ev_counted, s->compute);
+  }
+  if (e == hipSuccess) e = hipEventRecord(s->step_done[slot], s->compute);
+  lk.lock();
+  s->steps++;
+  s->blocks_run += n;
+  for (Request* r : finishing) {
+    if (e != hipSuccess) fail_request(r);
+    else r->state = ReqState::Counting;
+  }
+  if (e != hipSuccess)
+    for (Request* r : ready) fail_request(r);
+  return true;
+}
+
+// Counted requests get their records copied back; fetched ones complete.
+// Lock held.  Returns true on any progress.
+bool finish(fe_server* s) {
+  bool any = false;
+  for (size_t i = 0; i < s->active.size();) {
+    Request* r = s->active[i];
+    if (r->state == ReqState::Counting && hipEventQuery(r->ev_counted) == hipSuccess) {
+      r->n_out = (size_t)s->h_counts[r->slot];
+      const size_t bytes = std::max<size_t>(r->n_out * 16, 16);
+      const size_t off = s->host_arena.alloc(bytes);
+      if (off != SIZE_MAX) {
+        r->hout_off = off;
+        r->hout_len = bytes;
+        hipError_t e = r->n_out > r->cap ? hipErrorInvalidValue
+                                         : hipMemcpyAsync(s->host_base + off, s->dev_base + r->out_off,
+                                                          r->n_out * 16, hipMemcpyDeviceToHost, s->copy);
+        if (e == hipSuccess) e = hipEventRecord(r->ev_fetched, s->copy);
+        if (e != hipSuccess) fail_request(r);
+        else r->state = ReqState::Fetching;
+        any = true;
+      }
+    }
+    if (r->state == ReqState::Fetching && hipEventQuery(r->ev_fetched) == hipSuccess) {
+      r->state = ReqState::Done;
+      r->t_done = Clock::now();
+      s->completed++;
+      any = true;
+    }
+    if (r->state == ReqState::Done || r->state == ReqState::Failed) {
+      // the device side is no longer needed; the host output stays until fetched
+      if (r->dev_len) s->dev_arena.release(r->dev_off, r->dev_len);
+      if (r->tile_len) s->tile_arena.release(r->tile_base, r->tile_len);
+      if (r->hin_len) s->host_arena.release(r->hin_off, r->hin_len);
+      if (r->slot >= 0) s->free_slots.push_back(r->slot);
+      r->dev_len = r->tile_len = r->hin_len = 0;
+      r->slot = -1;
+      s->active.erase(s->active.begin() + i);
+      any = true;
+      continue;
+    }
+    ++i;
+  }
+  return any;
+}
+
+void worker_main(fe_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    bool progress = admit(s);
+    progress |= run_step(s, lk);
+    progress |= finish(s);
+    if (progress) {
+      s->cv.notify_all();
+      continue;
+    }
+    s->cv.wait_for(lk, std::chrono::microseconds(s->active.empty() ? 500 : 10));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, size_t host_budget,
+                           uint32_t max_slots, uint32_t step_blocks, fe_server** out) {
+  fe::clear_error();
+  if (!out || hbm_budget < (8u << 20) || host_budget < (1u << 20) || max_slots == 0 || step_blocks == 0)
+    return fe::fail(FE_ERR_INVALID, "bad server arguments");
+  *out = nullptr;
+  fe_status st = fe::check_params(p);
+  if (st != FE_OK) return st;
+  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "the server runs MNS only");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return fe::fail(FE_ERR_DEVICE, "no HIP device %d", device);
+  fe_server* s = new fe_server();
+  s->device = device;
+  s->params = *p;
+  s->L = fe::levels_of(p->b_max, p->b_min);
+  s->cells = 1 << (2 * (s->L - 1));
+  uint32_t gx[16], gy[16];
+  if (fe_tile_shapes(p->b_max, p->b_min, gx, gy, 16) == 0) {
+    delete s;
+    return fe::fail(FE_ERR_INVALID, "no kernel for these block sizes");
+  }
+  s->shape = fe::TileShape{(int)gx[0], (int)gy[0]};
+  s->max_slots = max_slots;
+  s->step_blocks = step_blocks;
+  // a quarter of the budget holds tile slots (records + masks), the rest
+  // images, outputs and ordering scratch
+  const size_t tile_bytes = (size_t)s->cells * 16 + 8;
+  const size_t tiles_cap = (hbm_budget / 4) / tile_bytes;
+  const size_t byte_budget = hbm_budget - tiles_cap * tile_bytes;
+  (void)hipSetDevice(device);
+  bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&s->dev_base), byte_budget) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * s->cells * 16) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->h_counts), (size_t)max_slots * 8, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&s->d_one), sizeof(fe::ImgDev)) == hipSuccess;
+  for (int k = 0; ok && k < 2; ++k)
+    ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc),
+                       hipHostMallocDefault) == hipSuccess &&
+         hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc)) ==
+             hipSuccess &&
+         hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
+  if (ok) {
+    fe::ImgDev one{};
+    ok = hipMemcpy(s->d_one, &one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) {
+    fe_server_destroy(s);
+    return fe::fail(FE_ERR_OOM, "server allocation failed");
+  }
+  s->dev_arena.reset(byte_budget, 256);
+  s->tile_arena.reset(tiles_cap, 16);
+  s->host_arena.reset(host_budget, 256);
+  for (int k = (int)max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return FE_OK;
+}
+
+void fe_server_destroy(fe_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->device);
+  if (s->compute) (void)hipStreamSynchronize(s->compute);
+  if (s->copy) (void)hipStreamSynchronize(s->copy);
+  for (auto& kv : s->all) {
+    release_request(s, kv.second);
+    delete kv.second;
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (s->h_desc[k]) (void)hipHostFree(s->h_desc[k]);
+    if (s->d_desc[k]) (void)hipFree(s->d_desc[k]);
+    if (s->step_done[k]) (void)hipEventDestroy(s->step_done[k]);
+  }
+  if (s->d_one) (void)hipFree(s->d_one);
+  if (s->dev_base) (void)hipFree(s->dev_base);
+  if (s->staging) (void)hipFree(s->staging);
+  if (s->masks) (void)hipFree(s->masks);
+  if (s->host_base) (void)hipHostFree(s->host_base);
+  if (s->h_counts) (void)hipHostFree(s->h_counts);
+  if (s->compute) (void)hipStreamDestroy(s->compute);
+  if (s->copy) (void)hipStreamDestroy(s->copy);
+  delete s;
+}
+
+fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
+                           uint64_t* req) {
+  fe::clear_error();
+  if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st = fe::check_shape(w, h, stride, s->params.b_max);
+  if (st != FE_OK) return st;
+  Request* r = new Request();
+  r->w = w;
+  r->h = h;
+  r->pitch = w;   // W is a multiple of b_max >= 4
+  r->tiles_x = w / s->params.b_max;
+  r->tiles_y = h / s->params.b_max;
+  r->groups_x = (r->tiles_x + s->shape.gx - 1) / s->shape.gx;
+  r->tiles = (uint64_t)r->tiles_x * r->tiles_y;
+  r->blocks = (uint64_t)r->groups_x * ((r->tiles_y + s->shape.gy - 1) / s->shape.gy);
+  r->cap = fe_max_transforms(w, h, s->params.b_min);
+  r->chunks = (size_t)((r->tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (byte_footprint(r) > s->dev_arena.size() || r->tiles > s->tile_arena.size()) {
+    delete r;
+    return fe::fail(FE_ERR_OOM, "request is larger than the server's device budget");
+  }
+  const size_t hin = s->host_arena.alloc((size_t)r->pitch * h);
+  if (hin == SIZE_MAX) {
+    delete r;
+    return fe::fail(FE_ERR_BUSY, "host staging is full");
+  }
+  r->hin_off = hin;
+  r->hin_len = (size_t)r->pitch * h;
+  uint8_t* dst = s->host_base + hin;
+  for (uint32_t y = 0; y < h; ++y) memcpy(dst + (size_t)y * r->pitch, h_img + (size_t)y * stride, w);
+  r->id = s->next_id++;
+  r->t_submit = Clock::now();
+  s->queued.push_back(r);
+  s->all[r->id] = r;
+  *req = r->id;
+  lk.unlock();
+  s->cv.notify_all();
+  return FE_OK;
+}
+
+fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t cap, size_t* n, int* done,
+                         double* latency_ms) {
+  fe::clear_error();
+  if (!s || !done) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(req);
+  if (it == s->all.end()) return fe::fail(FE_ERR_INVALID, "unknown request %llu", (unsigned long long)req);
+  Request* r = it->second;
+  if (r->state == ReqState::Failed) {
+    const fe_status e = r->error;
+    if (std::find(s->active.begin(), s->active.end(), r) == s->active.end()) {
+      release_request(s, r);
+      s->all.erase(it);
+      delete r;
+    }
+    return fe::fail(e, "request failed on the device");
+  }
+  if (r->state != ReqState::Done) {
+    *done = 0;
+    return FE_OK;
+  }
+  *done = 1;
+  if (n) *n = r->n_out;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (h_out) {
+    if (cap < r->n_out) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, r->n_out);
+    memcpy(h_out, s->host_base + r->hout_off, r->n_out * sizeof(fe_transform));
+    release_request(s, r);
+    s->all.erase(it);
+    delete r;
+  }
+  return FE_OK;
+}
+
+fe_status fe_server_stats(fe_server* s, uint64_t* steps, uint64_t* blocks, uint64_t* completed, size_t* hbm_used,
+                          uint32_t* in_flight, uint32_t* queued) {
+  fe::clear_error();
+  if (!s) return fe::fail(FE_ERR_INVALID, "NULL server");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (steps) *steps = s->steps;
+  if (blocks) *blocks = s->blocks_run;
+  if (completed) *completed = s->completed;
+  if (hbm_used) *hbm_used = s->dev_arena.used() + s->tile_arena.used() * ((size_t)s->cells * 16 + 8);
+  if (in_flight) *in_flight = (uint32_t)s->active.size();
+  if (queued) *queued = (uint32_t)s->queued.size();
+  return FE_OK;
+}
+
+}  // extern "C"
