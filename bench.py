@@ -84,6 +84,163 @@ def cpu_baseline(images, budget_s: float):
     return blocks / dt, used, recs, dt
 
 
+def pooled(fn, args, workers=8):
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(min(workers, os.cpu_count() or 1)) as ex:
+        return list(ex.map(fn, args))
+
+
+def _gen_c5(k):
+    from paper_1501_02894_amd import synth
+    return synth.c5_image(synth.c5_sides()[k])
+
+
+def _gen_named(name):
+    from paper_1501_02894_amd import synth
+    return synth.workload(name)
+
+
+def timed_kernel(fb, ctx, slot, fn, reps):
+    """Mean event-timed duration (ms) of kernel `slot` over reps calls of fn."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    fb.fe_timing_read(ctx.handle)
+    fb.fe_timing_enable(ctx.handle, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / reps
+    fb.fe_timing_enable(ctx.handle, False)
+    ms, cnt = fb.fe_timing_read(ctx.handle)
+    return (ms[slot] / cnt[slot] if cnt[slot] else float("nan")), cnt[slot] / reps, wall
+
+
+def bench_single(fb, ctx, img, b_max, b_min, thr, reps=10):
+    import torch
+    t = torch.from_numpy(img).cuda()
+    p = fb.make_params(b_max, b_min, thr)
+    out = torch.empty((fb.fe_max_transforms(img.shape[1], img.shape[0], b_min), 16), dtype=torch.uint8,
+                      device="cuda")
+    n = fb.fe_encode(ctx.handle, t, p, out=out).shape[0]
+    kms, _, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE, lambda: fb.fe_encode(ctx.handle, t, p, out=out), reps)
+    tiles = (img.shape[0] // b_max) * (img.shape[1] // b_max)
+    blocks = range_blocks(n, tiles)
+    return {"pixels": int(img.size), "records": n, "range_blocks": blocks, "kernel_ms": kms,
+            "call_ms": wall, "range_blocks_per_s": blocks / (wall / 1e3),
+            "kernel_GBps": (img.size + 16 * n + 8 * tiles) / (kms / 1e3) / 1e9}, out[:n]
+
+
+def bench_decode(fb, ctx, recs, w, h, b_max, iters=12, reps=3):
+    import torch
+    out = torch.empty((h, w), dtype=torch.uint8, device="cuda")
+    fn = lambda: fb.fe_decode(ctx.handle, recs, w, h, b_max, iters, out=out)
+    kms, per_call, wall = timed_kernel(fb, ctx, fb.FE_TIMING_DECODE, fn, reps)
+    # per iteration: each pixel's 2x2 domain means read (4 bytes, served from
+    # cache after the first touch: count the iterate once), one byte written,
+    # 16 bytes per transform
+    alg = 2 * w * h + 16 * int(recs.shape[0])
+    return {"iterations": iters, "iter_ms": kms, "call_ms": wall, "iter_GBps": alg / (kms / 1e3) / 1e9}, out
+
+
+def bench_fullsearch(fb, ctx, img, b_max, b_min, thr, reps=2):
+    import torch
+    t = torch.from_numpy(img).cuda()
+    p = fb.make_params(b_max, b_min, thr, full_search=True)
+    out = torch.empty((fb.fe_max_transforms(img.shape[1], img.shape[0], b_min), 16), dtype=torch.uint8,
+                      device="cuda")
+    recs = fb.to_records(fb.fe_encode(ctx.handle, t, p, out=out))
+    kms, launches, wall = timed_kernel(fb, ctx, fb.FE_TIMING_FULLSEARCH,
+                                       lambda: fb.fe_encode(ctx.handle, t, p, out=out), reps)
+    H, W = img.shape
+    R = (H // b_max) * (W // b_max)
+    macs = 0
+    for level in range(len(thr) + 1):
+        B = b_max >> level
+        macs += R * 8 * (W - 2 * B + 1) * (H - 2 * B + 1) * B * B
+        R = 4 * (R - int(np.sum(recs["level"] == level)))
+    search_ms = kms * launches
+    return {"records": int(recs.size), "search_ms": search_ms, "call_ms": wall, "int8_macs": macs,
+            "int8_TOPS": 2 * macs / (search_ms / 1e3) / 1e12,
+            "mfma_frac": 2 * macs / (search_ms / 1e3) / 5.0e15}
+
+
+def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
+    """Poisson arrivals at `rate`; returns served images/s and latency
+    percentiles (scheduled arrival -> records in host memory)."""
+    import threading
+    import torch
+    total = n_req + warmup
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, total))
+    which = rng.integers(0, len(pool), total)
+    done_at = np.zeros(total)
+    t0 = time.perf_counter() + 0.05
+    if mode == "server":
+        srv = fb.Server(B_MAX, B_MIN, THR, hbm_budget=16 << 30, host_budget=4 << 30, max_slots=512,
+                        step_blocks=2048)
+        ids = [None] * total
+        lat = np.zeros(total)
+
+        def submitter():
+            for i in range(total):
+                d = t0 + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                while True:
+                    try:
+                        ids[i] = srv.submit(pool[which[i]])
+                        break
+                    except fb.FeError as e:
+                        if e.status != fb.FE_ERR_BUSY:
+                            raise
+                        time.sleep(0.0002)
+                lat[i] = time.perf_counter() - (t0 + arrivals[i])   # submit delay
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        finished = 0
+        seen = np.zeros(total, bool)
+        while finished < total:
+            for i in range(total):
+                if seen[i] or ids[i] is None:
+                    continue
+                ok, recs, l = srv.poll(ids[i])
+                if ok:
+                    seen[i] = True
+                    finished += 1
+                    done_at[i] = time.perf_counter() - t0
+                    lat[i] += l / 1e3
+            time.sleep(0.0002)
+        th.join()
+        stats = srv.stats()
+        srv.close()
+    else:
+        p = fb.make_params(B_MAX, B_MIN, THR)
+        lat = np.zeros(total)
+        for i in range(total):
+            d = t0 + arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            im = pool[which[i]]
+            t = torch.from_numpy(im).cuda()
+            out = fb.fe_encode(ctx.handle, t, p)
+            recs = out.cpu()
+            now = time.perf_counter() - t0
+            done_at[i] = now
+            lat[i] = now - arrivals[i]
+        stats = None
+    m = slice(warmup, total)
+    span = done_at[m].max() - arrivals[m].min()
+    res = {"mode": mode, "rate": rate, "requests": n_req, "images_per_s": n_req / span,
+           "p50_ms": float(np.percentile(lat[m], 50) * 1e3), "p99_ms": float(np.percentile(lat[m], 99) * 1e3),
+           "mean_px": float(np.mean([pool[k].size for k in which[m]]))}
+    if stats:
+        res["steps"] = stats["steps"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +252,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain/cold comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for counter scaling)")
+    ap.add_argument("--serve-rates", default="200,1000,2000")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -221,6 +382,28 @@ def main():
         cold_ms = cms[fb.FE_TIMING_ENCODE] / max(1, ccnt[fb.FE_TIMING_ENCODE])
         result["cold"] = {"kernel_ms": cold_ms, "achieved_GBps": alg_bytes / (cold_ms / 1e3) / 1e9}
         del junk
+
+    if not args.no_extras:
+        from paper_1501_02894_amd import synth
+        c2, c3 = pooled(_gen_named, ["c2", "c3"], 2)
+        res_c2, _ = bench_single(fb, ctx, c2, 16, 4, [300, 200])
+        res_c3, recs_c3 = bench_single(fb, ctx, c3, 32, 4, [150, 100, 64], reps=5)
+        res_dec, _ = bench_decode(fb, ctx, recs_c3, 4096, 4096, 32)
+        res_fs = bench_fullsearch(fb, ctx, c2, 16, 4, [300, 200])
+        result["c2_single"] = res_c2
+        result["c3_single"] = res_c3
+        result["c3_decode"] = res_dec
+        result["c2_fullsearch"] = res_fs
+        print(f"[bench] single/decode/full-search done", file=sys.stderr, flush=True)
+
+    if not args.no_serving:
+        pool = pooled(_gen_c5, list(range(args.serve_pool)))
+        serving = []
+        for rate in [float(r) for r in args.serve_rates.split(",")]:
+            for mode in ("server", "plain"):
+                serving.append(serve_run(fb, mode, pool, rate, args.serve_requests, 30, 5, ctx=ctx))
+                print(f"[bench] serving {mode} @ {rate}/s: {serving[-1]}", file=sys.stderr, flush=True)
+        result["serving"] = serving
 
     if args.copy_calibration:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(3)
