@@ -180,8 +180,8 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     if mode == "server":
         srv = fb.Server(B_MAX, B_MIN, THR, hbm_budget=16 << 30, host_budget=4 << 30, max_slots=512,
                         step_blocks=2048)
-        ids = [None] * total
         lat = np.zeros(total)
+        index = {}
 
         def submitter():
             for i in range(total):
@@ -190,29 +190,29 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
                     time.sleep(d)
                 while True:
                     try:
-                        ids[i] = srv.submit(pool[which[i]])
+                        rid = srv.submit(pool[which[i]])
                         break
                     except fb.FeError as e:
                         if e.status != fb.FE_ERR_BUSY:
                             raise
                         time.sleep(0.0002)
                 lat[i] = time.perf_counter() - (t0 + arrivals[i])   # submit delay
+                index[rid] = i
 
         th = threading.Thread(target=submitter)
         th.start()
         finished = 0
-        seen = np.zeros(total, bool)
         while finished < total:
-            for i in range(total):
-                if seen[i] or ids[i] is None:
-                    continue
-                ok, recs, l = srv.poll(ids[i])
-                if ok:
-                    seen[i] = True
-                    finished += 1
-                    done_at[i] = time.perf_counter() - t0
-                    lat[i] += l / 1e3
-            time.sleep(0.0002)
+            rid = srv.wait(2000)          # blocks in the library, GIL released
+            if rid is None:
+                continue
+            ok, recs, l = srv.poll(rid)
+            while rid not in index:      # the submitter has not recorded it yet
+                time.sleep(0)
+            i = index[rid]
+            finished += 1
+            done_at[i] = time.perf_counter() - t0
+            lat[i] += l / 1e3
         th.join()
         stats = srv.stats()
         srv.close()
@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain/cold comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for counter scaling)")
-    ap.add_argument("--serve-rates", default="200,1000,2000")
+    ap.add_argument("--serve-rates", default="500,2000,8000")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--no-serving", action="store_true")

@@ -290,12 +290,14 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  * Encode server (continuous batching).  One parameter set per server.
  *
  * fe_server_create: device memory of `hbm_budget` bytes (a quarter holds
- * per-tile record slots and masks, the rest images, outputs and ordering
- * scratch) and `host_budget` bytes of pinned host memory for inputs and
- * results are reserved up front; at most `max_slots` requests are admitted
- * at once; one step launches the fused kernel over at most `step_blocks`
- * workgroup blocks of top tiles drawn first-come first-served from all
- * admitted requests.  A worker thread drives the steps.
+ * per-tile record slots and masks, the rest images and ordering scratch)
+ * and `host_budget` bytes of pinned host memory for inputs and results are
+ * reserved up front; at most `max_slots` requests are admitted at once; one
+ * step launches the fused kernel over at most `step_blocks` workgroup blocks
+ * of top tiles drawn first-come first-served from all admitted requests.
+ * A worker thread drives the steps.  The ordering kernel writes a finished
+ * request's records straight into its pinned result buffer, which stays
+ * reserved until the request is fetched: callers should poll promptly.
  *
  * fe_server_submit copies the host image (W x H, row pitch `stride`) into
  * pinned staging and queues it; the caller may reuse h_img on return.
@@ -312,6 +314,11 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  * returns FE_ERR_DEVICE and is released.  The stream equals fe_encode's for
  * the same image and parameters, whatever else was in flight.
  *
+ * fe_server_wait blocks up to `timeout_us` microseconds for a request to
+ * finish (done or failed) and returns its id, each finished id once, in
+ * completion order; FE_ERR_BUSY if none finished in time.  An id fetched by
+ * fe_server_poll before it was reported is not reported.
+ *
  * fe_server_destroy stops the worker, waits for the device and frees
  * everything, including unfetched results.  Submit / poll / stats may be
  * called from several threads.
@@ -324,6 +331,7 @@ fe_status fe_server_submit(fe_server* server, const uint8_t* h_img, uint32_t wid
                            uint32_t stride, uint64_t* req);
 fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, size_t cap, size_t* n,
                          int* done, double* latency_ms);
+fe_status fe_server_wait(fe_server* server, uint32_t timeout_us, uint64_t* req);
 fe_status fe_server_stats(fe_server* server, uint64_t* steps, uint64_t* blocks, uint64_t* completed,
                           size_t* hbm_used, uint32_t* in_flight, uint32_t* queued);
 void fe_server_destroy(fe_server* server);

@@ -80,6 +80,7 @@ _SIGNATURES = {
     "fe_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_SZ), ctypes.POINTER(_U32),
                                        ctypes.POINTER(_U32)]),
+    "fe_server_wait": (ctypes.c_int, [_VP, _U32, ctypes.POINTER(ctypes.c_uint64)]),
     "fe_server_destroy": (None, [_VP]),
     "fe_tile_shapes": (ctypes.c_int, [_U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.c_int]),
     "fe_set_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, _U32, _U32]),
@@ -341,6 +342,16 @@ def fe_server_poll(server: int, req: int, fetch: bool = True):
     return True, out[: n.value], lat.value
 
 
+def fe_server_wait(server: int, timeout_us: int):
+    """Id of the next finished request, or None if none finished in time."""
+    req = ctypes.c_uint64(0)
+    st = load().fe_server_wait(server, int(timeout_us), ctypes.byref(req))
+    if st == FE_ERR_BUSY:
+        return None
+    _check(st)
+    return req.value
+
+
 def fe_server_stats(server: int) -> dict:
     v = [ctypes.c_uint64(0) for _ in range(3)]
     used = _SZ(0)
@@ -368,6 +379,9 @@ class Server:
 
     def poll(self, req, fetch=True):
         return fe_server_poll(self.handle, req, fetch)
+
+    def wait(self, timeout_us=1000):
+        return fe_server_wait(self.handle, timeout_us)
 
     def stats(self):
         return fe_server_stats(self.handle)

@@ -11,10 +11,12 @@
 //      top tiles taken first-come first-served from every admitted request
 //      whose image has arrived: mixed image sizes share the launch, and a
 //      large image is spread over several steps;
-//   3. a request whose last block has run gets its stream ordered on the
-//      device and its record count copied back; when the count arrives, the
-//      records themselves are copied back (exactly that many) and the
-//      request completes.
+//   3. a request whose last block has run gets its stream ordered by a
+//      kernel that writes the records and their count straight into the
+//      request's pinned host buffer; the request completes when that
+//      kernel's event has fired.
+// The compute stream waits for a request's image copy on the device
+// (stream-event wait), so the host never round-trips between stages.
 // Records of a request live in its own tile slots, so they do not depend on
 // what else shares the steps.
 #include <hip/hip_runtime.h>
@@ -88,7 +90,7 @@ class Arena {
   size_t size_ = 0, used_ = 0, g_ = 1;
 };
 
-enum class ReqState { Queued, Copying, Running, Counting, Fetching, Done, Failed };
+enum class ReqState { Queued, Running, Ordering, Done, Failed };
 
 struct Request {
   uint64_t id = 0;
@@ -99,11 +101,11 @@ struct Request {
   size_t chunks = 0;
   size_t hin_off = 0, hin_len = 0;       // pinned host input copy
   size_t dev_off = 0, dev_len = 0;       // byte arena region
-  size_t img_off = 0, out_off = 0, ofs_off = 0, csum_off = 0, cbase_off = 0;
+  size_t img_off = 0, csum_off = 0, cbase_off = 0;
   size_t tile_base = 0, tile_len = 0;    // tile arena range
-  size_t hout_off = 0, hout_len = 0;     // pinned host output
-  int slot = -1;                         // pinned count slot
-  hipEvent_t ev_copied = nullptr, ev_counted = nullptr, ev_fetched = nullptr;
+  size_t hout_off = 0, hout_len = 0;     // pinned host output: records, then 2 x u64 offsets
+  int slot = -1;                         // admission slot: owns ev_copied / ev_done of that slot
+  bool waited = false;                   // compute stream already waits on the copy event
   ReqState state = ReqState::Queued;
   size_t n_out = 0;
   Clock::time_point t_submit, t_done;
@@ -122,7 +124,6 @@ struct fe_server {
   uint4* staging = nullptr;              // tile arena: record slots
   uint64_t* masks = nullptr;             // tile arena: occupancy
   uint8_t* host_base = nullptr;          // pinned host arena
-  uint64_t* h_counts = nullptr;          // pinned: one record count per slot
   Arena dev_arena, tile_arena, host_arena;
   std::vector<int> free_slots;
   uint32_t max_slots = 0, step_blocks = 0;
@@ -131,9 +132,11 @@ struct fe_server {
   fe::BlockDesc* d_desc[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
   int step_slot = 0;
+  std::vector<hipEvent_t> ev_copied, ev_done;   // per admission slot
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv, done_cv;
   std::deque<Request*> queued;
+  std::deque<uint64_t> completions;      // finished ids not yet reported by fe_server_wait
   std::vector<Request*> active;          // admitted, not yet done
   std::map<uint64_t, Request*> all;      // by id, until fetched
   uint64_t next_id = 1;
@@ -146,11 +149,14 @@ namespace {
 
 size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Device byte footprint of a request (image, output, offsets, ordering
-// scratch); its tile slots are accounted in the tile arena.
+// Device byte footprint of a request (image and ordering scratch); its
+// tile slots are accounted in the tile arena, its output in pinned host
+// memory.
 size_t byte_footprint(const Request* r) {
-  return r256((size_t)r->pitch * r->h) + r256(r->cap * 16) + 256 + r256(r->chunks * 4) + r256((r->chunks + 1) * 8);
+  return r256((size_t)r->pitch * r->h) + r256(r->chunks * 4) + r256((r->chunks + 1) * 8);
 }
+
+size_t host_out_bytes(const Request* r) { return r->cap * 16 + 16; }
 
 void release_request(fe_server* s, Request* r) {
   if (r->dev_len) s->dev_arena.release(r->dev_off, r->dev_len);
@@ -160,11 +166,13 @@ void release_request(fe_server* s, Request* r) {
   if (r->slot >= 0) s->free_slots.push_back(r->slot);
   r->dev_len = r->tile_len = r->hin_len = r->hout_len = 0;
   r->slot = -1;
-  for (hipEvent_t* e : {&r->ev_copied, &r->ev_counted, &r->ev_fetched})
-    if (*e) {
-      (void)hipEventDestroy(*e);
-      *e = nullptr;
-    }
+}
+
+// Release a fetched request and drop it from the completion queue.
+void forget(fe_server* s, Request* r) {
+  release_request(s, r);
+  auto c = std::find(s->completions.begin(), s->completions.end(), r->id);
+  if (c != s->completions.end()) s->completions.erase(c);
 }
 
 void fail_request(Request* r) {
@@ -172,10 +180,11 @@ void fail_request(Request* r) {
   r->error = FE_ERR_DEVICE;
 }
 
-// Admit queued requests in arrival order while slots and memory allow.
-// Lock held.
-bool admit(fe_server* s) {
-  bool any = false;
+// Admit queued requests in arrival order while slots and memory allow, and
+// start their image copies.  Lock held on entry and exit; released while
+// the copies are issued.
+bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
+  std::vector<Request*> adm;
   while (!s->queued.empty() && !s->free_slots.empty()) {
     Request* r = s->queued.front();
     const size_t need = byte_footprint(r);
@@ -186,46 +195,54 @@ bool admit(fe_server* s) {
       s->dev_arena.release(off, need);
       break;
     }
+    const size_t hout = s->host_arena.alloc(host_out_bytes(r));
+    if (hout == SIZE_MAX) {
+      s->tile_arena.release(tb, r->tiles);
+      s->dev_arena.release(off, need);
+      break;
+    }
     s->queued.pop_front();
-    any = true;
     r->dev_off = off;
     r->dev_len = need;
     r->img_off = off;
-    r->out_off = r->img_off + r256((size_t)r->pitch * r->h);
-    r->ofs_off = r->out_off + r256(r->cap * 16);
-    r->csum_off = r->ofs_off + 256;
+    r->csum_off = r->img_off + r256((size_t)r->pitch * r->h);
     r->cbase_off = r->csum_off + r256(r->chunks * 4);
+    r->hout_off = hout;
+    r->hout_len = host_out_bytes(r);
     r->tile_base = tb;
     r->tile_len = r->tiles;
     r->slot = s->free_slots.back();
     s->free_slots.pop_back();
-    hipError_t e = hipEventCreateWithFlags(&r->ev_copied, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_counted, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_fetched, hipEventDisableTiming);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
-                         hipMemcpyHostToDevice, s->copy);
+    s->active.push_back(r);       // still Queued: run_step skips it
+    adm.push_back(r);
+  }
+  if (adm.empty()) return false;
+  // only this thread touches admitted requests' device state
+  lk.unlock();
+  std::vector<char> ok(adm.size(), 0);
+  for (size_t k = 0; k < adm.size(); ++k) {
+    Request* r = adm[k];
+    hipError_t e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
+                                  hipMemcpyHostToDevice, s->copy);
     if (e == hipSuccess)
       e = fe::launch_zero_u32(reinterpret_cast<uint32_t*>(s->masks + r->tile_base), (size_t)r->tiles * 2, s->copy);
-    if (e == hipSuccess) e = hipEventRecord(r->ev_copied, s->copy);
-    if (e != hipSuccess) {
-      fail_request(r);
-    } else {
-      r->state = ReqState::Copying;
-    }
-    s->active.push_back(r);
+    if (e == hipSuccess) e = hipEventRecord(s->ev_copied[r->slot], s->copy);
+    ok[k] = e == hipSuccess;
   }
-  return any;
+  lk.lock();
+  for (size_t k = 0; k < adm.size(); ++k) {
+    if (ok[k]) adm[k]->state = ReqState::Running;
+    else fail_request(adm[k]);
+  }
+  return true;
 }
 
 // One step: a single launch over up to step_blocks blocks.  Returns true if
 // it launched work.  Lock held on entry and exit.
 bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   std::vector<Request*> ready;
-  for (Request* r : s->active) {
-    if (r->state == ReqState::Copying && hipEventQuery(r->ev_copied) == hipSuccess) r->state = ReqState::Running;
+  for (Request* r : s->active)
     if (r->state == ReqState::Running && r->next_block < r->blocks) ready.push_back(r);
-  }
   if (ready.empty()) return false;
   const int slot = s->step_slot;
   s->step_slot ^= 1;
@@ -234,9 +251,13 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   lk.lock();
   fe::BlockDesc* hd = s->h_desc[slot];
   uint32_t n = 0;
-  std::vector<Request*> finishing;
+  std::vector<Request*> finishing, first_time;
   for (Request* r : ready) {
     if (n >= s->step_blocks) break;
+    if (!r->waited) {
+      first_time.push_back(r);
+      r->waited = true;
+    }
     while (r->next_block < r->blocks && n < s->step_blocks) {
       const uint64_t b = r->next_block++;
       const uint32_t gyi = (uint32_t)(b / r->groups_x), gxi = (uint32_t)(b - (uint64_t)gyi * r->groups_x);
@@ -252,8 +273,11 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     if (r->next_block == r->blocks) finishing.push_back(r);
   }
   lk.unlock();
-  hipError_t e = hipMemcpyAsync(s->d_desc[slot], hd, (size_t)n * sizeof(fe::BlockDesc), hipMemcpyHostToDevice,
-                                s->compute);
+  hipError_t e = hipSuccess;
+  for (Request* r : first_time)
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copied[r->slot], 0);   // image, cleared masks
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_desc[slot], hd, (size_t)n * sizeof(fe::BlockDesc), hipMemcpyHostToDevice, s->compute);
   if (e == hipSuccess) {
     fe::EncodeArgs a{};
     a.blocks = s->d_desc[slot];
@@ -267,15 +291,14 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   }
   for (Request* r : finishing) {
     if (e != hipSuccess) break;
+    // records and offsets go straight to the pinned host output
+    uint8_t* hout = s->host_base + r->hout_off;
     e = fe::launch_scatter(s->d_one, 1, r->tiles, s->cells, s->masks + r->tile_base,
                            reinterpret_cast<uint32_t*>(s->dev_base + r->csum_off),
                            reinterpret_cast<uint64_t*>(s->dev_base + r->cbase_off),
-                           s->staging + r->tile_base * (size_t)s->cells,
-                           reinterpret_cast<uint4*>(s->dev_base + r->out_off), r->cap,
-                           reinterpret_cast<uint64_t*>(s->dev_base + r->ofs_off), s->compute);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&s->h_counts[r->slot], s->dev_base + r->ofs_off + 8, 8, hipMemcpyDeviceToHost, s->compute);
-    if (e == hipSuccess) e = hipEventRecord(r->ev_counted, s->compute);
+                           s->staging + r->tile_base * (size_t)s->cells, reinterpret_cast<uint4*>(hout), r->cap,
+                           reinterpret_cast<uint64_t*>(hout + r->cap * 16), s->compute);
+    if (e == hipSuccess) e = hipEventRecord(s->ev_done[r->slot], s->compute);
   }
   if (e == hipSuccess) e = hipEventRecord(s->step_done[slot], s->compute);
   lk.lock();
@@ -283,37 +306,25 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   s->blocks_run += n;
   for (Request* r : finishing) {
     if (e != hipSuccess) fail_request(r);
-    else r->state = ReqState::Counting;
+    else r->state = ReqState::Ordering;
   }
   if (e != hipSuccess)
     for (Request* r : ready) fail_request(r);
   return true;
 }
 
-// Counted requests get their records copied back; fetched ones complete.
-// Lock held.  Returns true on any progress.
+// Requests whose ordering kernel has finished complete.  Lock held.
+// Returns true on any progress.
 bool finish(fe_server* s) {
   bool any = false;
   for (size_t i = 0; i < s->active.size();) {
     Request* r = s->active[i];
-    if (r->state == ReqState::Counting && hipEventQuery(r->ev_counted) == hipSuccess) {
-      r->n_out = (size_t)s->h_counts[r->slot];
-      const size_t bytes = std::max<size_t>(r->n_out * 16, 16);
-      const size_t off = s->host_arena.alloc(bytes);
-      if (off != SIZE_MAX) {
-        r->hout_off = off;
-        r->hout_len = bytes;
-        hipError_t e = r->n_out > r->cap ? hipErrorInvalidValue
-                                         : hipMemcpyAsync(s->host_base + off, s->dev_base + r->out_off,
-                                                          r->n_out * 16, hipMemcpyDeviceToHost, s->copy);
-        if (e == hipSuccess) e = hipEventRecord(r->ev_fetched, s->copy);
-        if (e != hipSuccess) fail_request(r);
-        else r->state = ReqState::Fetching;
-        any = true;
-      }
-    }
-    if (r->state == ReqState::Fetching && hipEventQuery(r->ev_fetched) == hipSuccess) {
-      r->state = ReqState::Done;
+    if (r->state == ReqState::Ordering && hipEventQuery(s->ev_done[r->slot]) == hipSuccess) {
+      uint64_t total = 0;
+      memcpy(&total, s->host_base + r->hout_off + r->cap * 16 + 8, 8);
+      r->n_out = (size_t)total;
+      r->state = r->n_out <= r->cap ? ReqState::Done : ReqState::Failed;
+      if (r->state == ReqState::Failed) r->error = FE_ERR_DEVICE;
       r->t_done = Clock::now();
       s->completed++;
       any = true;
@@ -327,6 +338,7 @@ bool finish(fe_server* s) {
       r->dev_len = r->tile_len = r->hin_len = 0;
       r->slot = -1;
       s->active.erase(s->active.begin() + i);
+      s->completions.push_back(r->id);
       any = true;
       continue;
     }
@@ -339,14 +351,20 @@ void worker_main(fe_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
-    bool progress = admit(s);
+    bool progress = admit(s, lk);
     progress |= run_step(s, lk);
+    const size_t before = s->completions.size();
     progress |= finish(s);
-    if (progress) {
-      s->cv.notify_all();
-      continue;
+    if (s->completions.size() != before) s->done_cv.notify_all();
+    if (progress) continue;
+    if (s->active.empty()) {
+      s->cv.wait_for(lk, std::chrono::microseconds(500));
+    } else {
+      // work is on the device: poll its events without sleeping
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
     }
-    s->cv.wait_for(lk, std::chrono::microseconds(s->active.empty() ? 500 : 10));
   }
 }
 
@@ -391,8 +409,6 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
             hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * s->cells * 16) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc(reinterpret_cast<void**>(&s->h_counts), (size_t)max_slots * 8, hipHostMallocDefault) ==
-                hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->d_one), sizeof(fe::ImgDev)) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
     ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc),
@@ -400,6 +416,11 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
          hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc)) ==
              hipSuccess &&
          hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
+  s->ev_copied.assign(max_slots, nullptr);
+  s->ev_done.assign(max_slots, nullptr);
+  for (uint32_t k = 0; ok && k < max_slots; ++k)
+    ok = hipEventCreateWithFlags(&s->ev_copied[k], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&s->ev_done[k], hipEventDisableTiming) == hipSuccess;
   if (ok) {
     fe::ImgDev one{};
     ok = hipMemcpy(s->d_one, &one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
@@ -437,12 +458,15 @@ void fe_server_destroy(fe_server* s) {
     if (s->d_desc[k]) (void)hipFree(s->d_desc[k]);
     if (s->step_done[k]) (void)hipEventDestroy(s->step_done[k]);
   }
+  for (hipEvent_t ev : s->ev_copied)
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : s->ev_done)
+    if (ev) (void)hipEventDestroy(ev);
   if (s->d_one) (void)hipFree(s->d_one);
   if (s->dev_base) (void)hipFree(s->dev_base);
   if (s->staging) (void)hipFree(s->staging);
   if (s->masks) (void)hipFree(s->masks);
   if (s->host_base) (void)hipHostFree(s->host_base);
-  if (s->h_counts) (void)hipHostFree(s->h_counts);
   if (s->compute) (void)hipStreamDestroy(s->compute);
   if (s->copy) (void)hipStreamDestroy(s->copy);
   delete s;
@@ -477,10 +501,17 @@ fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint3
   }
   r->hin_off = hin;
   r->hin_len = (size_t)r->pitch * h;
-  uint8_t* dst = s->host_base + hin;
-  for (uint32_t y = 0; y < h; ++y) memcpy(dst + (size_t)y * r->pitch, h_img + (size_t)y * stride, w);
-  r->id = s->next_id++;
   r->t_submit = Clock::now();
+  lk.unlock();
+  // the staging region is reserved: copy into it without holding the lock
+  uint8_t* dst = s->host_base + hin;
+  if (stride == r->pitch) {
+    memcpy(dst, h_img, (size_t)r->pitch * h);
+  } else {
+    for (uint32_t y = 0; y < h; ++y) memcpy(dst + (size_t)y * r->pitch, h_img + (size_t)y * stride, w);
+  }
+  lk.lock();
+  r->id = s->next_id++;
   s->queued.push_back(r);
   s->all[r->id] = r;
   *req = r->id;
@@ -500,7 +531,7 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
   if (r->state == ReqState::Failed) {
     const fe_status e = r->error;
     if (std::find(s->active.begin(), s->active.end(), r) == s->active.end()) {
-      release_request(s, r);
+      forget(s, r);
       s->all.erase(it);
       delete r;
     }
@@ -516,10 +547,21 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
   if (h_out) {
     if (cap < r->n_out) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, r->n_out);
     memcpy(h_out, s->host_base + r->hout_off, r->n_out * sizeof(fe_transform));
-    release_request(s, r);
+    forget(s, r);
     s->all.erase(it);
     delete r;
   }
+  return FE_OK;
+}
+
+fe_status fe_server_wait(fe_server* s, uint32_t timeout_us, uint64_t* req) {
+  fe::clear_error();
+  if (!s || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), [s] { return !s->completions.empty(); }))
+    return fe::fail(FE_ERR_BUSY, "no request finished within %u us", timeout_us);
+  *req = s->completions.front();
+  s->completions.pop_front();
   return FE_OK;
 }
 

@@ -131,3 +131,22 @@ def test_server_errors(torch_dev):
         assert done and recs.size == n.value
         with pytest.raises(fb.FeError):
             srv.poll(r)                                       # released
+
+
+def test_server_wait_reports_each_once(torch_dev, ctx):
+    imgs = mixed_images(12, 4, 64, 384)
+    with fb.Server(16, 4, THR, max_slots=6, step_blocks=32) as srv:
+        assert srv.wait(100) is None                         # nothing submitted
+        reqs = [srv.submit(im) for im in imgs]
+        seen = []
+        t0 = time.time()
+        while len(seen) < len(reqs):
+            rid = srv.wait(10000)
+            if rid is not None:
+                seen.append(rid)
+            assert time.time() - t0 < 60, f"only {len(seen)} of {len(reqs)} reported"
+        assert sorted(seen) == sorted(reqs)
+        assert srv.wait(1000) is None                        # each id once
+        for k, r in enumerate(reqs):
+            done, recs, _ = srv.poll(r)
+            assert done and recs.tobytes() == alone(torch_dev, ctx, imgs[k]).tobytes()
