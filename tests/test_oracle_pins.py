@@ -487,3 +487,54 @@ def test_fullsearch_stream_tiles_image():
     rec = fullsearch.encode(img, 8, 4, [300])
     decode.decode(rec, 32, 32, 8, 2)
     assert _preorder(rec, 32, 32, 8) == list(range(rec.size))
+
+
+def _decode_step_by_definition(rec, start, b_max):
+    """One Jacobi step written out pixel by pixel in exact rationals."""
+    H, W = start.shape
+    X = start.astype(np.int64)
+    out = np.full((H, W), -1, np.int64)
+
+    def domain(x0, y0, B):
+        dx = min(max(x0 - B // 2, 0), W - 2 * B)
+        dy = min(max(y0 - B // 2, 0), H - 2 * B)
+        big = X[dy:dy + 2 * B, dx:dx + 2 * B]
+        return np.array([[int(Fraction(int(big[2 * a:2 * a + 2, 2 * b:2 * b + 2].sum()), 4) + Fraction(1, 2))
+                          for b in range(B)] for a in range(B)])
+
+    def paint(x0, y0, t, dsum, s, lum):
+        B = t.shape[0]
+        dbar = Fraction(int(dsum), B * B)
+        for i in range(B):
+            for j in range(B):
+                v = s * (int(t[i, j]) - dbar) + lum
+                out[y0 + i, x0 + j] = min(max(int(v + Fraction(1, 2)), 0), 255)
+
+    for r in rec:
+        B = b_max >> int(r["level"])
+        x, y = int(r["x"]), int(r["y"])
+        if int(r["flags"]) & 1 == 0:
+            d = domain(x, y, B)
+            paint(x, y, geometric_isometry(d, int(r["iso"])), d.sum(), Fraction(int(r["s_idx"]), 8), int(r["lum"]))
+        else:
+            b = B // 2
+            m = int(r["lum"])
+            O = [m + int(v) for v in r["dlum"]]
+            O.append(4 * m - sum(O))                       # eq. (1)
+            c1, c2 = mns.PHASE2_SETS[int(r["level"]) + 1]
+            for c in range(4):
+                cx, cy = x + (c % 2) * b, y + (c // 2) * b
+                d = domain(cx, cy, b)
+                s = Fraction([c1, c2][(int(r["s_idx"]) >> c) & 1], 20)
+                paint(cx, cy, d, d.sum(), s, O[c])
+    assert np.all(out >= 0), "records do not cover the image"
+    return out
+
+
+def test_decoder_one_step_by_definition(c1_stream):
+    img, rec = c1_stream
+    assert np.any(rec["flags"] & 1) and np.any(rec["iso"] >= 4)
+    rng = np.random.default_rng(11)
+    start = rng.integers(0, 256, (64, 64)).astype(np.uint8)
+    want = _decode_step_by_definition(rec, start, 8)
+    np.testing.assert_array_equal(decode.decode(rec, 64, 64, 8, 1, start=start).astype(np.int64), want)
