@@ -215,39 +215,39 @@ struct Lds {
   uint32_t img[G::IMG_W];
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
-  uint32_t meta[4][2][G::CAPW];
-  uint32_t fit[4][G::CAPW];
-  uint32_t mom[4][5][G::CAPW];
-  uint32_t pmeta[4][G::PCAPW];
-  uint32_t pm[4][G::PCAPW];
+  uint32_t meta[4][2][G::CAPW];    // per wave: range lists of two consecutive levels
+  uint32_t par[4][2][G::PCAPW];    // per wave: their parents, meta | m << 24
   unsigned long long mask[G::NT];
 };
 
+// Lane `src` of the wave's value v.
+__device__ __forceinline__ int lane_read(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
 // The quadtree of one block, each wave on its own tiles.  Uses only LDS
 // data staged for the block; writes records to staging and tile masks.
+//
+// One pass per level over the wave's list of ranges, a team of T lanes per
+// range: the team accumulates the range's moments and reduces them so that
+// every lane of the team holds the totals; every lane then fits the range.
+// From level 2 on the list holds the four children (Z order) of each range
+// that failed the level above, in consecutive teams, so the same pass also
+// runs the parent's phase 2 (Technique 1) across the four teams.  Accepted
+// ranges are written at once; failed ones are compacted (ballot prefix) into
+// the next level's parent list and their children into its range list.
 template <int BMAX, int L, int GX, int GY>
 __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm) {
   using G = Geo<BMAX, L, GX, GY>;
   const Region& rg = bg.rg;
   const int gx = bg.gx, gy = bg.gy;
   const int tid = threadIdx.x;
-  uint32_t* s_img = sm.img;
-  uint32_t* s_h0 = sm.h0;
-  uint32_t* s_h0t = sm.h0t;
-  auto& s_meta = sm.meta;
-  auto& s_fit = sm.fit;
-  auto& s_mom = sm.mom;
-  auto& s_pmeta = sm.pmeta;
-  auto& s_pm = sm.pm;
+  const uint32_t* s_img = sm.img;
+  const uint32_t* s_h0 = sm.h0;
+  const uint32_t* s_h0t = sm.h0t;
   unsigned long long* s_mask = sm.mask;
-  // ---- 2. each wave runs the quadtree of its own tiles, independently
   const int wave = tid >> 6, lane = tid & 63;
   const int t_first = wave * G::NTW;
-  uint32_t* w_meta0 = s_meta[wave][0];
-  uint32_t* w_meta1 = s_meta[wave][1];
-  uint32_t* w_fit = s_fit[wave];
-  uint32_t* w_pmeta = s_pmeta[wave];
-  uint32_t* w_pm = s_pm[wave];
+  uint32_t* w_meta0 = sm.meta[wave][0];
+  uint32_t* w_meta1 = sm.meta[wave][1];
   // this wave's tiles of the block that lie inside the image
   const int my_t = t_first + lane;
   const bool my_valid = lane < G::NTW && (my_t & (GX - 1)) < gx && (my_t >> G::LOG_GX) < gy;
@@ -260,14 +260,16 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
 
   int n = (int)__popcll(vbal);  // ranges in the current list (wave-uniform)
   for (int lev = 1; lev <= L; ++lev) {
-    uint32_t* cur = (lev & 1) ? w_meta0 : w_meta1;
+    const uint32_t* cur = (lev & 1) ? w_meta0 : w_meta1;
     uint32_t* nxt = (lev & 1) ? w_meta1 : w_meta0;
+    const uint32_t* ppar = sm.par[wave][(lev - 1) & 1];   // parents of `cur` (level lev-1)
+    uint32_t* npar = sm.par[wave][lev & 1];               // parents of `nxt`
     const bool last = lev == L;
     const uint32_t thr = last ? 0u : a.thr[lev - 1];
     const int B = BMAX >> (lev - 1);
+    uint32_t nfail = 0;
 
-    // moments + phase-1 fit of the listed ranges (team of T lanes per range)
-    auto moments_fit = [&](auto bconst) {
+    auto level_pass = [&](auto bconst) {
       constexpr int BB = decltype(bconst)::value;
       constexpr bool ALIGNED = BB >= 16;
       int T = 1;
@@ -276,12 +278,16 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
       for (int base = 0; base < n * T; base += 64) {
         const int idx = base + lane;
         const int e = idx >> logT, t = idx & (T - 1);
+        const bool valid = e < n;
+        // ---- moments of range e (the team's rows t, t + T, ...)
         uint32_t acc[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] = 0u;
-        if (e < n) {
-          int X, Y;
-          range_xy<BMAX, G::BMIN, G::LOG_GX>(cur[e], rg, X, Y);
+        uint32_t meta = 0;
+        int X = 0, Y = 0;
+        if (valid) {
+          meta = cur[e];
+          range_xy<BMAX, G::BMIN, G::LOG_GX>(meta, rg, X, Y);
           const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
           const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
           const int rx = X - rg.X0, ry = Y - rg.Y0;
@@ -290,103 +296,63 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             accumulate_row_pair<BB, ALIGNED>(s_img, ry * G::TPITCH + rx, G::TPITCH, s_h0, wy * G::HP + wx,
                                              G::HP, s_h0t, wx * G::TP + wy, G::TP, i, acc);
         }
-        team_reduce(acc, T);
-        if (e < n && t == 0) {
-          w_fit[e] = fit_phase1<BB>(acc, last, thr);
-#pragma unroll
-          for (int s = 0; s < 5; ++s) s_mom[wave][s][e] = acc[s];
-        }
-      }
-    };
-    if constexpr (BMAX >= 32) { if (B == 32) moments_fit(std::integral_constant<int, 32>{}); }
-    if constexpr (BMAX >= 16 && G::BMIN <= 16) { if (B == 16) moments_fit(std::integral_constant<int, 16>{}); }
-    if constexpr (BMAX >= 8 && G::BMIN <= 8) { if (B == 8) moments_fit(std::integral_constant<int, 8>{}); }
-    if constexpr (G::BMIN <= 4) { if (B == 4) moments_fit(std::integral_constant<int, 4>{}); }
-    wave_sync();
+        team_reduce(acc, T);   // butterfly: every lane of the team holds the totals
+        const uint32_t fit = fit_phase1<BB>(acc, last, thr);
 
-    // phase 2 of the parents that failed at level lev-1: their children are
-    // exactly the ranges just fitted, four per parent in Z order, so each
-    // lane takes one child and the four lanes of a quad combine by DPP
-    if (lev >= 2 && a.phase2) {
-      auto phase2 = [&](auto bconst) {
-        constexpr int BB = decltype(bconst)::value;   // child side
-        constexpr int LOGNB = 2 * Log2<BB>::value;
-        constexpr double NB = (double)(BB * BB);
-        int c1, c2, delta;
-        phase2_consts(lev - 1, c1, c2, delta);
-        const double thr2 = (400.0 * NB * NB) * (double)a.thr[lev - 2];
-        const double a1 = (double)(c1 * c1), b1 = (double)(40 * c1);
-        const double a2 = (double)(c2 * c2), b2 = (double)(40 * c2);
-        for (int base = 0; base < n; base += 64) {
-          const int e = base + lane, c = lane & 3, p = e >> 2;
-          const bool valid = e < n;
-          uint32_t sr = 0, srr = 0, sd = 0, sdd = 0, srd = 0;
-          int m = 0;
-          if (valid) {
-            sr = s_mom[wave][0][e];
-            srr = s_mom[wave][1][e];
-            sd = s_mom[wave][2][e];
-            sdd = s_mom[wave][3][e];
-            srd = s_mom[wave][4][e];
-            m = (int)w_pm[p];
-          }
-          int O = (int)((2u * sr + (uint32_t)(BB * BB)) >> (LOGNB + 1));
-          const int O0 = dpp_i<0x00>(O), O1 = dpp_i<0x55>(O), O2 = dpp_i<0xAA>(O);
-          if (c == 3) O = 4 * m - O0 - O1 - O2;                      // eq. (1)
-          const double dsr = (double)sr, dsd = (double)sd;
-          const double Q = NB * (double)sdd - dsd * dsd;
-          const double P = NB * (double)srd - dsr * dsd;
-          const double R = NB * (double)srr - dsr * dsr;
-          const double f1 = a1 * Q - b1 * P;
-          const double f2 = a2 * Q - b2 * P;
-          const bool use2 = f2 < f1;
-          const double dm = (double)O * NB - dsr;
-          const double S = (use2 ? f2 : f1) + 400.0 * R + 400.0 * (dm * dm);
-          int ok = (valid && O - m <= delta && m - O <= delta && O >= 0 && O <= 255 && S < thr2) ? 1 : 0;
-          ok &= dpp_i<0xB1>(ok);
-          ok &= dpp_i<0x4E>(ok);
-          int bits = use2 ? (1 << c) : 0;
-          bits |= dpp_i<0xB1>(bits);
-          bits |= dpp_i<0x4E>(bits);
-          if (ok) {
-            w_fit[e] |= kFitDead;
-            if (c == 0) {
-              const uint32_t pmeta = w_pmeta[p];
-              int X, Y;
-              range_xy<BMAX, G::BMIN, G::LOG_GX>(pmeta, rg, X, Y);
+        // ---- phase 2 of the parent of this group of four children
+        bool dead = false;   // the parent was stored by phase 2
+        if constexpr (BB < BMAX) {
+          if (a.phase2) {
+            constexpr int LOGNB = 2 * Log2<BB>::value;
+            constexpr double NB = (double)(BB * BB);
+            int c1, c2, delta;
+            phase2_consts(lev - 1, c1, c2, delta);
+            const double thr2 = (400.0 * NB * NB) * (double)a.thr[lev - 2];
+            const int c = e & 3;
+            const int g0 = lane - c * T;               // lane of child 0 (same t)
+            const uint32_t pe = valid ? ppar[e >> 2] : 0u;
+            const int m = (int)(pe >> 24);
+            int O = (int)((2u * acc[0] + (uint32_t)(BB * BB)) >> (LOGNB + 1));
+            const int O0 = lane_read(O, g0), O1 = lane_read(O, g0 + T), O2 = lane_read(O, g0 + 2 * T);
+            if (c == 3) O = 4 * m - O0 - O1 - O2;   // eq. (1)
+            const double dsr = (double)acc[0], dsd = (double)acc[2];
+            const double Q = NB * (double)acc[3] - dsd * dsd;
+            const double P = NB * (double)acc[4] - dsr * dsd;
+            const double R = NB * (double)acc[1] - dsr * dsr;
+            const double f1 = (double)(c1 * c1) * Q - (double)(40 * c1) * P;
+            const double f2 = (double)(c2 * c2) * Q - (double)(40 * c2) * P;
+            const bool use2 = f2 < f1;
+            const double dm = (double)O * NB - dsr;
+            const double S = (use2 ? f2 : f1) + 400.0 * R + 400.0 * (dm * dm);
+            const bool okc = valid && O - m <= delta && m - O <= delta && O >= 0 && O <= 255 && S < thr2;
+            const uint64_t okb = __ballot(okc), u2b = __ballot(valid && use2);
+            const uint64_t pat = 1ull | (1ull << T) | (1ull << (2 * T)) | (1ull << (3 * T));
+            dead = valid && ((okb >> g0) & pat) == pat;
+            if (dead && c == 0 && t == 0) {
+              const uint64_t ub = u2b >> g0;
+              const int bits = (int)((ub & 1ull) | (((ub >> T) & 1ull) << 1) | (((ub >> (2 * T)) & 1ull) << 2) |
+                                     (((ub >> (3 * T)) & 1ull) << 3));
+              const uint32_t pmeta = pe & 0x00ffffffu;
+              int PX, PY;
+              range_xy<BMAX, G::BMIN, G::LOG_GX>(pmeta, rg, PX, PY);
               constexpr int PB = 2 * BB;
-              const int dx = clampi(X - PB / 2, 0, rg.W - 2 * PB);
-              const int dy = clampi(Y - PB / 2, 0, rg.H - 2 * PB);
+              const int pdx = clampi(PX - PB / 2, 0, rg.W - 2 * PB);
+              const int pdy = clampi(PY - PB / 2, 0, rg.H - 2 * PB);
               const int cell = morton(pmeta);
               a.staging[tile_global<G::LOG_GX>(pmeta, rg) * G::CELLS + cell] =
-                  make_record(X, Y, dx, dy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
+                  make_record(PX, PY, pdx, pdy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
               atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
             }
           }
         }
-      };
-      if constexpr (BMAX >= 32 && G::BMIN <= 16) { if (B == 16) phase2(std::integral_constant<int, 16>{}); }
-      if constexpr (BMAX >= 16 && G::BMIN <= 8) { if (B == 8) phase2(std::integral_constant<int, 8>{}); }
-      if constexpr (BMAX >= 8 && G::BMIN <= 4) { if (B == 4) phase2(std::integral_constant<int, 4>{}); }
-      wave_sync();
-    }
 
-    // store accepted ranges; compact failures (ballot prefix) into the
-    // parent list and their children into the next level's list
-    uint32_t nfail = 0;
-    for (int base = 0; base < n; base += 64) {
-      const int e = base + lane;
-      bool fail = false;
-      uint32_t meta = 0, fit = 0;
-      if (e < n) {
-        meta = cur[e];
-        fit = w_fit[e];
-        if (!(fit & kFitDead)) {
+        // ---- store accepted ranges; compact failures into the next lists
+        const bool lead = valid && t == 0 && !dead;
+        bool fail = false;
+        if (lead) {
           if (fit & kFitAccept) {
-            int X, Y;
-            range_xy<BMAX, G::BMIN, G::LOG_GX>(meta, rg, X, Y);
-            const int dx = clampi(X - B / 2, 0, rg.W - 2 * B);
-            const int dy = clampi(Y - B / 2, 0, rg.H - 2 * B);
+            const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
+            const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
             const int cell = morton(meta);
             a.staging[tile_global<G::LOG_GX>(meta, rg) * G::CELLS + cell] =
                 make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
@@ -396,21 +362,24 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             fail = true;
           }
         }
-      }
-      const uint64_t bal = __ballot(fail);
-      const uint32_t q = nfail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      if (fail) {
-        w_pmeta[q] = meta;
-        w_pm[q] = fit & 0xffu;
-        const uint32_t half = (uint32_t)(B / 2 / G::BMIN);
-        const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
+        const uint64_t bal = __ballot(fail);
+        if (fail) {
+          const uint32_t q = nfail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          npar[q] = meta | ((fit & 0xffu) << 24);
+          const uint32_t half = (uint32_t)(BB / 2 / G::BMIN);
+          const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
 #pragma unroll
-        for (uint32_t c = 0; c < 4; ++c)
-          nxt[4 * q + c] = tile | ((cy + (c >> 1) * half) << 8) | (cx + (c & 1u) * half);
+          for (uint32_t ch = 0; ch < 4; ++ch)
+            nxt[4 * q + ch] = tile | ((cy + (ch >> 1) * half) << 8) | (cx + (ch & 1u) * half);
+        }
+        nfail += (uint32_t)__popcll(bal);
       }
-      nfail += (uint32_t)__popcll(bal);
-    }
+    };
+    if constexpr (BMAX >= 32) { if (B == 32) level_pass(std::integral_constant<int, 32>{}); }
+    if constexpr (BMAX >= 16 && G::BMIN <= 16) { if (B == 16) level_pass(std::integral_constant<int, 16>{}); }
+    if constexpr (BMAX >= 8 && G::BMIN <= 8) { if (B == 8) level_pass(std::integral_constant<int, 8>{}); }
+    if constexpr (G::BMIN <= 4) { if (B == 4) level_pass(std::integral_constant<int, 4>{}); }
     wave_sync();
     n = (int)(4 * nfail);
     if (last || n == 0) break;

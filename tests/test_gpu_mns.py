@@ -144,12 +144,35 @@ def test_encode_strided_input(torch_dev, ctx):
     assert_same_stream(got, mns.encode(img, 16, 4, [300, 200]))
 
 
-def test_encode_every_tile_shape(torch_dev, ctx):
-    """The stream does not depend on the workgroup tile shape."""
-    img = synth.noise_1f(320, 224, 41)
-    want = mns.encode(img, 16, 4, [300, 200])
-    got = fb.to_records(ctx.encode(dev(torch_dev, img), 16, 4, [300, 200]))
-    assert_same_stream(got, want)
+@pytest.mark.parametrize("b_max,b_min,thr,H,W", [
+    (16, 4, [300, 200], 320, 224), (16, 8, [300], 160, 96), (16, 16, [], 96, 48),
+    (32, 4, [150, 100, 64], 256, 320), (32, 8, [200, 100], 192, 128), (32, 16, [200], 96, 64),
+    (8, 4, [400], 104, 88), (4, 4, [], 36, 20),
+])
+@pytest.mark.parametrize("layout", ["aligned", "unaligned"])
+def test_encode_every_tile_shape(torch_dev, ctx, b_max, b_min, thr, H, W, layout):
+    """The stream depends neither on the workgroup tile shape nor on the
+    kernel variant: 16-byte aligned inputs with b_max >= 16 take the
+    persistent kernel that copies regions into LDS asynchronously, others
+    (here: base offset 4, odd pitch) the one that loads them directly."""
+    img = synth.noise_1f(H, W, 41 + b_max + H)
+    want = mns.encode(img, b_max, b_min, thr)
+    if layout == "aligned":
+        t = dev(torch_dev, img)
+    else:
+        buf = np.zeros((H, W + 12), np.uint8)
+        buf[:, 4:W + 4] = img
+        t = dev(torch_dev, buf)[:, 4:W + 4]
+    shapes = fb.fe_tile_shapes(b_max, b_min)
+    assert shapes
+    try:
+        for gx, gy in shapes:
+            log(f"  shape {gx}x{gy} {layout}")
+            fb.fe_set_tile_shape(ctx.handle, b_max, b_min, gx, gy)
+            got = fb.to_records(ctx.encode(t, b_max, b_min, thr))
+            assert_same_stream(got, want)
+    finally:
+        fb.fe_set_tile_shape(ctx.handle, b_max, b_min, 0, 0)
 
 
 def test_capacity_error(torch_dev, ctx):
