@@ -224,14 +224,17 @@ __device__ __forceinline__ uint4 make_record(int x, int y, int dx, int dy, int l
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Four round-half-up 2x2 means of an 8-wide, 2-row pixel group:
-// a0/a1 = row 0 pixels 0-3 / 4-7, b0/b1 = row 1.
+// a0/a1 = row 0 pixels 0-3 / 4-7, b0/b1 = row 1.  Sums of two pixel pairs
+// are formed in 16-bit fields (even bytes masked, odd bytes moved down by a
+// byte permute); each field is below 2^10, so after the shift by 2 its low
+// byte is the mean and a final permute packs the four bytes.
 __device__ __forceinline__ uint32_t mean2x2_x4(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
-  const uint32_t M = 0x00FF00FFu;
-  uint32_t s0 = (a0 & M) + ((a0 >> 8) & M) + (b0 & M) + ((b0 >> 8) & M) + 0x00020002u;
-  uint32_t s1 = (a1 & M) + ((a1 >> 8) & M) + (b1 & M) + ((b1 >> 8) & M) + 0x00020002u;
-  s0 = (s0 >> 2) & M;
-  s1 = (s1 >> 2) & M;
-  return __builtin_amdgcn_perm(s1, s0, 0x06040200u);
+  const uint32_t M = 0x00FF00FFu, ODD = 0x0c030c01u;   // bytes 1, 3 -> 0, 2
+  const uint32_t s0 = (a0 & M) + (b0 & M) + __builtin_amdgcn_perm(0u, a0, ODD) + __builtin_amdgcn_perm(0u, b0, ODD) +
+                      0x00020002u;
+  const uint32_t s1 = (a1 & M) + (b1 & M) + __builtin_amdgcn_perm(0u, a1, ODD) + __builtin_amdgcn_perm(0u, b1, ODD) +
+                      0x00020002u;
+  return __builtin_amdgcn_perm(s1 >> 2, s0 >> 2, 0x06040200u);
 }
 
 }  // namespace fe

@@ -569,10 +569,10 @@ static hipError_t launch_one(const EncodeArgs& a, hipStream_t s) {
   X(4, 1, 16, 16) X(4, 1, 32, 8)                                                        \
   X(8, 1, 16, 8) X(8, 1, 8, 8) X(8, 2, 8, 8) X(8, 2, 16, 4) X(8, 2, 4, 4) X(8, 2, 8, 4)  \
   X(16, 1, 8, 4) X(16, 1, 4, 4) X(16, 2, 8, 4) X(16, 2, 4, 4) X(16, 2, 8, 2)             \
-  X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2) X(16, 3, 8, 2) X(16, 3, 4, 2)            \
-  X(16, 3, 16, 4)                                                                       \
+  X(16, 3, 8, 8) X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2) X(16, 3, 8, 2)            \
+  X(16, 3, 4, 2) X(16, 3, 16, 4)                                                        \
   X(32, 1, 4, 2) X(32, 1, 2, 2) X(32, 2, 4, 2) X(32, 2, 2, 2) X(32, 3, 4, 2)             \
-  X(32, 3, 2, 2) X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1) X(32, 4, 4, 1)
+  X(32, 3, 2, 2) X(32, 4, 4, 4) X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1) X(32, 4, 4, 1)
 
 int encode_shapes(int b_max, int levels, TileShape* out, int max_out) {
   int k = 0;

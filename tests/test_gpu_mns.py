@@ -149,12 +149,11 @@ def test_encode_strided_input(torch_dev, ctx):
     (32, 4, [150, 100, 64], 256, 320), (32, 8, [200, 100], 192, 128), (32, 16, [200], 96, 64),
     (8, 4, [400], 104, 88), (4, 4, [], 36, 20),
 ])
-@pytest.mark.parametrize("layout", ["aligned", "unaligned"])
+@pytest.mark.parametrize("layout", ["aligned", "offset4"])
 def test_encode_every_tile_shape(torch_dev, ctx, b_max, b_min, thr, H, W, layout):
     """The stream depends neither on the workgroup tile shape nor on the
-    kernel variant: 16-byte aligned inputs with b_max >= 16 take the
-    persistent kernel that copies regions into LDS asynchronously, others
-    (here: base offset 4, odd pitch) the one that loads them directly."""
+    input's placement: a dense image, and a view at byte offset 4 with pitch
+    W + 12 (not 16-byte aligned)."""
     img = synth.noise_1f(H, W, 41 + b_max + H)
     want = mns.encode(img, b_max, b_min, thr)
     if layout == "aligned":
@@ -173,6 +172,15 @@ def test_encode_every_tile_shape(torch_dev, ctx, b_max, b_min, thr, H, W, layout
             assert_same_stream(got, want)
     finally:
         fb.fe_set_tile_shape(ctx.handle, b_max, b_min, 0, 0)
+
+
+def test_misaligned_input_rejected(torch_dev, ctx):
+    """Images must be 4-byte aligned with a pitch that is a multiple of 4."""
+    buf = dev(torch_dev, np.zeros((64, 64 + 13), np.uint8))
+    for view in (buf[:, 3:67], buf[:, :64]):          # offset 3; pitch 77
+        with pytest.raises(fb.FeError) as ei:
+            ctx.encode(view, 16, 4, [300, 200])
+        assert ei.value.status == fb.FE_ERR_SHAPE
 
 
 def test_capacity_error(torch_dev, ctx):
