@@ -36,6 +36,7 @@ namespace {
 
 template <int BMAX, int L, int GX, int GY>
 struct Geo {
+  static constexpr int BMAXV = BMAX;
   static constexpr int BMIN = BMAX >> (L - 1);
   static constexpr int NT = GX * GY;                          // tiles per workgroup
   static constexpr int LOG_GX = Log2<GX>::value;
@@ -177,16 +178,31 @@ struct Stage {
           }
         }
       }
-      // tile pixels (tile edges are multiples of 4 pixels)
+      // tile pixels.  For b_max >= 8 the tile block starts at a multiple of
+      // 8 pixels from the region origin in both directions and spans a
+      // multiple of 8, so a group lies wholly inside or outside it; for
+      // b_max = 4 tile edges are multiples of 4 and rows/halves are tested.
+      if constexpr (G::BMAXV >= 8) {
+        const int gy0 = b.rg.ay0 + 8 * g;
+        if (gy0 >= b.rg.Y0 && gy0 < b.ty_end && x >= b.rg.X0 && x < b.tx_end) {
+          uint32_t* dst = s_img + (gy0 - b.rg.Y0) * (G::TPITCH / 4) + ((x - b.rg.X0) >> 2);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int y = b.rg.ay0 + 8 * g + r;
-        if (y < b.rg.Y0 || y >= b.ty_end) continue;
+          for (int r = 0; r < 8; ++r) {
+            dst[r * (G::TPITCH / 4)] = v[r][0];
+            dst[r * (G::TPITCH / 4) + 1] = v[r][1];
+          }
+        }
+      } else {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int xx = x + 4 * h;
-          if (xx >= b.rg.X0 && xx < b.tx_end)
-            s_img[(y - b.rg.Y0) * (G::TPITCH / 4) + ((xx - b.rg.X0) >> 2)] = v[r][h];
+        for (int r = 0; r < 8; ++r) {
+          const int y = b.rg.ay0 + 8 * g + r;
+          if (y < b.rg.Y0 || y >= b.ty_end) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int xx = x + 4 * h;
+            if (xx >= b.rg.X0 && xx < b.tx_end)
+              s_img[(y - b.rg.Y0) * (G::TPITCH / 4) + ((xx - b.rg.X0) >> 2)] = v[r][h];
+          }
         }
       }
       // 2x2 means: H0 rows 4g .. 4g+3, columns 4 c8 .. 4 c8 + 3
