@@ -227,6 +227,29 @@ fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_i
                           uint64_t* d_offsets, size_t* n_out, void* stream);
 
 /*
+ * Recorded batch encode (a HIP graph).  fe_plan_create validates the batch
+ * as fe_encode_batch does, allocates the plan's own scratch (record slots
+ * and masks for every top tile, block descriptors, ordering scratch),
+ * uploads the image table and records the launch sequence once.
+ * fe_plan_launch replays it on `stream`: the images are re-read in place
+ * (their contents may change between launches, their addresses and sizes
+ * may not), and the stream and offsets are written to d_out / d_offsets as
+ * fe_encode_batch writes them; the caller reads d_offsets[n_imgs] and checks
+ * it against cap.  Launches on one plan must not overlap; fe_plan_destroy
+ * waits for the device.  The plan keeps the context's tile shape at
+ * creation and uses the context for kernel timing (fe_timing_*): while
+ * timing is enabled each launch's encode and ordering kernels are timed as
+ * in eager calls.  The context must outlive the plan.  For callers that encode the same set of buffers repeatedly
+ * (video frames, a fixed input ring).
+ */
+typedef struct fe_plan fe_plan;
+fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
+                         const fe_params* params, fe_transform* d_out, size_t cap,
+                         uint64_t* d_offsets, fe_plan** out);
+fe_status fe_plan_launch(fe_plan* plan, void* stream);
+void fe_plan_destroy(fe_plan* plan);
+
+/*
  * Decode (Sec. 1): start from d_start (W x H, dense) or mid-grey 128 if
  * d_start is NULL, and apply the n transforms `iters` times; every
  * iteration computes all pixels from the previous iterate (Jacobi).  A

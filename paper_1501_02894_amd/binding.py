@@ -70,6 +70,10 @@ _SIGNATURES = {
                                  ctypes.POINTER(_SZ), _VP]),
     "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
+    "fe_plan_create": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params), _VP, _SZ,
+                                      _VP, ctypes.POINTER(_VP)]),
+    "fe_plan_launch": (ctypes.c_int, [_VP, _VP]),
+    "fe_plan_destroy": (None, [_VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
     "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
@@ -209,19 +213,16 @@ def fe_encode(ctx: int, img, params: fe_params, out=None, stream=None):
 
 
 def fe_encode_batch(ctx: int, imgs, params: fe_params, out=None, offsets=None, wait: bool = True,
-                    stream=None):
+                    stream=None, descs=None):
     """Returns (out, offsets, n): image k's stream is out[offsets[k]:offsets[k+1]].
-    With wait=False the call does not synchronise and n is None."""
+    With wait=False the call does not synchronise and n is None.  `descs`
+    (from image_descs) may be passed to reuse a descriptor array."""
     import torch
-    descs = (fe_image_desc * len(imgs))()
-    cap = 0
-    for k, im in enumerate(imgs):
-        H, W = im.shape
-        descs[k].data = _ptr(im)
-        descs[k].width, descs[k].height, descs[k].stride, descs[k].reserved = W, H, im.stride(0), 0
-        cap += fe_max_transforms(W, H, params.b_min)
+    if descs is None:
+        descs = _descs(imgs)
     dev = imgs[0].device
     if out is None:
+        cap = sum(fe_max_transforms(im.shape[1], im.shape[0], params.b_min) for im in imgs)
         out = torch.empty((cap, 16), dtype=torch.uint8, device=dev)
     if offsets is None:
         offsets = torch.zeros(len(imgs) + 1, dtype=torch.int64, device=dev)
@@ -229,6 +230,52 @@ def fe_encode_batch(ctx: int, imgs, params: fe_params, out=None, offsets=None, w
     _check(load().fe_encode_batch(ctx, descs, len(imgs), ctypes.byref(params), _ptr(out), out.shape[0],
                                   _ptr(offsets), ctypes.byref(n) if wait else None, _stream(stream)))
     return out, offsets, (n.value if wait else None)
+
+
+def image_descs(imgs):
+    """fe_image_desc array of device images (2-D uint8 tensors)."""
+    return _descs(imgs)
+
+
+def fe_plan_create(ctx: int, imgs, params: fe_params, out, offsets) -> int:
+    """Record a batch encode of `imgs` into `out` / `offsets` (device tensors
+    that must outlive the plan)."""
+    descs = _descs(imgs)
+    h = _VP()
+    _check(load().fe_plan_create(ctx, descs, len(imgs), ctypes.byref(params), _ptr(out), out.shape[0],
+                                 _ptr(offsets), ctypes.byref(h)))
+    return h.value
+
+
+def fe_plan_launch(plan: int, stream=None) -> None:
+    _check(load().fe_plan_launch(plan, _stream(stream)))
+
+
+def fe_plan_destroy(plan: int) -> None:
+    load().fe_plan_destroy(plan)
+
+
+class Plan:
+    """Recorded batch encode; keeps references to its buffers."""
+
+    def __init__(self, ctx, imgs, b_max, b_min, thresholds, out, offsets, phase2=True):
+        self.imgs, self.out, self.offsets = list(imgs), out, offsets
+        self.handle = fe_plan_create(ctx.handle, self.imgs, make_params(b_max, b_min, thresholds, phase2), out,
+                                     offsets)
+
+    def launch(self, stream=None):
+        fe_plan_launch(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            fe_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: int, start=None, out=None,

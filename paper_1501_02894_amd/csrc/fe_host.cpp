@@ -61,6 +61,29 @@ struct fe_ctx {
   int ev_used = 0;
 };
 
+// A recorded batch encode (hipGraph) with its own scratch.
+struct fe_plan {
+  int device = 0;
+  uint32_t n_imgs = 0;
+  fe::ImgDev* d_table = nullptr;
+  fe::BlockDesc* blocks = nullptr;
+  uint4* staging = nullptr;
+  uint64_t* masks = nullptr;
+  uint32_t* chunk_sum = nullptr;
+  uint64_t* chunk_base = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // event-record nodes around the encode and ordering kernels: they record
+  // the plan's own events, or a pair of the context's timing events while
+  // timing is enabled
+  fe_ctx* ctx = nullptr;
+  hipEvent_t own[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphNode_t tnode[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;        // all four nodes found
+  bool on_ctx = false;       // nodes currently point at context events
+};
+
 namespace {
 
 struct DeviceGuard {
@@ -153,17 +176,29 @@ fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, hipStream_t
   return FE_OK;
 }
 
-// Shared MNS encode of a list of images with common parameters.
-fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
-                        fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
-  const int L = fe::levels_of(p->b_max, p->b_min);
-  const int bmax = (int)p->b_max;
-  const fe::TileShape shape = pick_shape(ctx, bmax, L);
-  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
-  const int cells = 1 << (2 * (L - 1));
-  std::vector<fe::ImgDev> table(n_imgs);
-  uint64_t tiles = 0;
-  uint32_t wgs = 0;
+// Arguments of a batch encode (fe_encode_batch, fe_plan_create).
+fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p, const fe_transform* d_out,
+                      const uint64_t* d_offsets) {
+  if (!h_imgs || !d_out || !d_offsets || n_imgs == 0) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st = fe::check_params(p);
+  if (st != FE_OK) return st;
+  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
+  if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
+  for (uint32_t k = 0; k < n_imgs; ++k) {
+    if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
+    if ((st = fe::check_shape(h_imgs[k].width, h_imgs[k].height, h_imgs[k].stride, p->b_max)) != FE_OK) return st;
+    if ((uintptr_t)h_imgs[k].data & 3) return fe::fail(FE_ERR_SHAPE, "image %u must be 4-byte aligned", k);
+  }
+  return FE_OK;
+}
+
+// Image table of a batch for `shape`: per image its tiles, workgroup blocks,
+// first workgroup and first tile.  Returns the totals.
+fe_status build_table(const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p, fe::TileShape shape,
+                      std::vector<fe::ImgDev>& table, uint64_t& tiles, uint32_t& wgs) {
+  table.assign(n_imgs, fe::ImgDev{});
+  tiles = 0;
+  wgs = 0;
   for (uint32_t k = 0; k < n_imgs; ++k) {
     fe::ImgDev& d = table[k];
     d.data = imgs[k].data;
@@ -182,8 +217,23 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
     wgs += (uint32_t)g;
     tiles += (uint64_t)d.tiles_x * d.tiles_y;
   }
+  return FE_OK;
+}
+
+// Shared MNS encode of a list of images with common parameters.
+fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
+                        fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  const int bmax = (int)p->b_max;
+  const fe::TileShape shape = pick_shape(ctx, bmax, L);
+  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
+  const int cells = 1 << (2 * (L - 1));
+  std::vector<fe::ImgDev> table;
+  uint64_t tiles = 0;
+  uint32_t wgs = 0;
+  fe_status st = build_table(imgs, n_imgs, p, shape, table, tiles, wgs);
+  if (st != FE_OK) return st;
   const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
-  fe_status st;
   if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
@@ -429,16 +479,9 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, u
 fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p,
                           fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, void* stream) {
   fe::clear_error();
-  if (!ctx || !h_imgs || !d_out || !d_offsets || n_imgs == 0) return fe::fail(FE_ERR_INVALID, "NULL argument");
-  fe_status st = fe::check_params(p);
+  if (!ctx) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st = check_batch(h_imgs, n_imgs, p, d_out, d_offsets);
   if (st != FE_OK) return st;
-  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
-  if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
-  for (uint32_t k = 0; k < n_imgs; ++k) {
-    if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
-    if ((st = fe::check_shape(h_imgs[k].width, h_imgs[k].height, h_imgs[k].stride, p->b_max)) != FE_OK) return st;
-    if ((uintptr_t)h_imgs[k].data & 3) return fe::fail(FE_ERR_SHAPE, "image %u must be 4-byte aligned", k);
-  }
   DeviceGuard g(ctx->device);
   return encode_images(ctx, h_imgs, n_imgs, p, d_out, cap, d_offsets, n_out, (hipStream_t)stream);
 }
@@ -617,6 +660,191 @@ fe_status fe_timing_read(fe_ctx* ctx, double* ms, uint64_t* launches, uint32_t n
   }
   ctx->ev_used = 0;
   return FE_OK;
+}
+
+// ---------------------------------------------------------------- plans
+}  // extern "C"
+
+namespace {
+
+// Nodes of a linear graph in dependency order (empty if not a chain).
+std::vector<hipGraphNode_t> chain_of(hipGraph_t g) {
+  std::vector<hipGraphNode_t> out;
+  size_t nroots = 0;
+  if (hipGraphGetRootNodes(g, nullptr, &nroots) != hipSuccess || nroots != 1) return {};
+  hipGraphNode_t cur = nullptr;
+  if (hipGraphGetRootNodes(g, &cur, &nroots) != hipSuccess) return {};
+  while (cur) {
+    out.push_back(cur);
+    size_t nd = 0;
+    if (hipGraphNodeGetDependentNodes(cur, nullptr, &nd) != hipSuccess || nd > 1) return {};
+    hipGraphNode_t next = nullptr;
+    if (nd == 1 && hipGraphNodeGetDependentNodes(cur, &next, &nd) != hipSuccess) return {};
+    cur = nd == 1 ? next : nullptr;
+  }
+  return out;
+}
+
+// Splice event-record nodes into a copy of the plan's chain
+// [prep, encode, order...]: own[0] between prep and encode, own[1] and
+// own[2] between encode and the first ordering kernel, own[3] after the
+// last.  Instantiates the copy.  Returns false (and leaves the plan
+// untouched) if any step fails.
+bool add_timing_nodes(fe_plan* pl) {
+  hipGraph_t g = nullptr;
+  if (hipGraphClone(&g, pl->graph) != hipSuccess) return false;
+  bool ok = false;
+  do {
+    std::vector<hipGraphNode_t> c = chain_of(g);
+    if (c.size() < 3) break;
+    hipGraphNode_t prep = c[0], enc = c[1], ord = c[2], last = c.back();
+    hipGraphNode_t n[4] = {};
+    if (hipGraphAddEventRecordNode(&n[0], g, &prep, 1, pl->own[0]) != hipSuccess) break;
+    if (hipGraphAddDependencies(g, &n[0], &enc, 1) != hipSuccess) break;
+    if (hipGraphAddEventRecordNode(&n[1], g, &enc, 1, pl->own[1]) != hipSuccess) break;
+    if (hipGraphAddEventRecordNode(&n[2], g, &enc, 1, pl->own[2]) != hipSuccess) break;
+    if (hipGraphAddDependencies(g, &n[1], &ord, 1) != hipSuccess) break;
+    if (hipGraphAddDependencies(g, &n[2], &ord, 1) != hipSuccess) break;
+    if (hipGraphAddEventRecordNode(&n[3], g, &last, 1, pl->own[3]) != hipSuccess) break;
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) break;
+    // node handles of the instantiated copy are those of `g`
+    for (int k = 0; k < 4; ++k) pl->tnode[k] = n[k];
+    (void)hipGraphDestroy(pl->graph);
+    pl->graph = g;
+    pl->exec = ex;
+    ok = true;
+  } while (false);
+  if (!ok) (void)hipGraphDestroy(g);
+  return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p,
+                         fe_transform* d_out, size_t cap, uint64_t* d_offsets, fe_plan** out) {
+  fe::clear_error();
+  if (!ctx || !out) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  fe_status st = check_batch(h_imgs, n_imgs, p, d_out, d_offsets);
+  if (st != FE_OK) return st;
+  DeviceGuard g(ctx->device);
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  const int bmax = (int)p->b_max;
+  const fe::TileShape shape = pick_shape(ctx, bmax, L);
+  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
+  std::vector<fe::ImgDev> table;
+  uint64_t tiles = 0;
+  uint32_t wgs = 0;
+  if ((st = build_table(h_imgs, n_imgs, p, shape, table, tiles, wgs)) != FE_OK) return st;
+  const int cells = 1 << (2 * (L - 1));
+  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  fe_plan* pl = new fe_plan();
+  pl->device = ctx->device;
+  pl->n_imgs = n_imgs;
+  // device table: the ImgDev entries followed by their wg_first words
+  const size_t slots = n_imgs + (n_imgs * sizeof(uint32_t) + sizeof(fe::ImgDev) - 1) / sizeof(fe::ImgDev);
+  std::vector<fe::ImgDev> host(slots);
+  memcpy(host.data(), table.data(), n_imgs * sizeof(fe::ImgDev));
+  uint32_t* wf = reinterpret_cast<uint32_t*>(host.data() + n_imgs);
+  for (uint32_t k = 0; k < n_imgs; ++k) wf[k] = table[k].wg_first;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_table), slots * sizeof(fe::ImgDev));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->blocks), std::max<size_t>(wgs, 1) * sizeof(fe::BlockDesc));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->staging), std::max<size_t>(tiles * cells, 1) * 16);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->masks), std::max<size_t>(tiles, 1) * 8);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_sum), std::max<size_t>(chunks, 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_base), (chunks + 1) * 8);
+  if (e == hipSuccess) e = hipMemcpy(pl->d_table, host.data(), slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreate(&pl->own[k]);
+  if (e != hipSuccess) {
+    fe_plan_destroy(pl);
+    return hip_fail(e, "plan allocation");
+  }
+  pl->ctx = ctx;
+  // record the launch sequence once; replays re-read the images in place
+  fe::EncodeArgs a{};
+  a.imgs = pl->d_table;
+  a.wg_first = reinterpret_cast<const uint32_t*>(pl->d_table + n_imgs);
+  a.blocks = pl->blocks;
+  a.n_imgs = n_imgs;
+  a.n_wg = wgs;
+  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
+  a.staging = pl->staging;
+  a.masks = pl->masks;
+  e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = fe::launch_block_prep(pl->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, pl->blocks, pl->capture);
+    if (le == hipSuccess) le = fe::launch_mns_tiles(bmax, L, shape, a, pl->capture);
+    if (le == hipSuccess)
+      le = fe::launch_scatter(pl->d_table, n_imgs, tiles, cells, pl->masks, pl->chunk_sum, pl->chunk_base,
+                              pl->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, d_offsets, pl->capture);
+    e = hipStreamEndCapture(pl->capture, &pl->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e != hipSuccess) {
+    fe_plan_destroy(pl);
+    return hip_fail(e, "plan capture");
+  }
+  // The capture is a chain: prep, encode, then the ordering kernels.  A
+  // copy of it gets event-record nodes before and after the encode kernel
+  // and after the last ordering kernel (for timing); if that fails, the
+  // plain chain is used and launches are not timed.
+  pl->timed = add_timing_nodes(pl);
+  if (!pl->timed) {
+    e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      fe_plan_destroy(pl);
+      return hip_fail(e, "plan instantiate");
+    }
+  }
+  *out = pl;
+  return FE_OK;
+}
+
+fe_status fe_plan_launch(fe_plan* pl, void* stream) {
+  fe::clear_error();
+  if (!pl) return fe::fail(FE_ERR_INVALID, "NULL plan");
+  DeviceGuard g(pl->device);
+  fe_ctx* c = pl->ctx;
+  if (pl->timed) {
+    // point the event nodes at two fresh pairs of the context's timing
+    // events (a node update takes effect from the next launch on)
+    if (c && c->timing && c->ev && c->ev_used + 2 <= fe_ctx::kTimingCap) {
+      const int i = c->ev_used++, j = c->ev_used++;
+      c->ev_slot[i] = FE_TIMING_ENCODE;
+      c->ev_slot[j] = FE_TIMING_SCATTER;
+      const hipEvent_t evs[4] = {c->ev[2 * i], c->ev[2 * i + 1], c->ev[2 * j], c->ev[2 * j + 1]};
+      for (int k = 0; k < 4; ++k)
+        FE_HIP(hipGraphExecEventRecordNodeSetEvent(pl->exec, pl->tnode[k], evs[k]), "plan timing node");
+      pl->on_ctx = true;
+    } else if (pl->on_ctx) {
+      for (int k = 0; k < 4; ++k)
+        FE_HIP(hipGraphExecEventRecordNodeSetEvent(pl->exec, pl->tnode[k], pl->own[k]), "plan timing node");
+      pl->on_ctx = false;
+    }
+  }
+  FE_HIP(hipGraphLaunch(pl->exec, (hipStream_t)stream), "plan launch");
+  return FE_OK;
+}
+
+void fe_plan_destroy(fe_plan* pl) {
+  if (!pl) return;
+  DeviceGuard g(pl->device);
+  if (pl->capture) (void)hipStreamSynchronize(pl->capture);
+  (void)hipDeviceSynchronize();   // no replay may still use the buffers
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->capture) (void)hipStreamDestroy(pl->capture);
+  for (hipEvent_t ev : pl->own)
+    if (ev) (void)hipEventDestroy(ev);
+  for (void* q : {(void*)pl->d_table, (void*)pl->blocks, (void*)pl->staging, (void*)pl->masks,
+                  (void*)pl->chunk_sum, (void*)pl->chunk_base})
+    if (q) (void)hipFree(q);
+  delete pl;
 }
 
 }  // extern "C"

@@ -164,17 +164,28 @@ struct Stage {
       if (4 * g >= b.hrows || c8 >= b.n8) continue;
       const int x = b.rg.ax0 + 8 * c8;
       uint32_t v[8][2];
+      const uint8_t* row0 = b.data + (size_t)(b.rg.ay0 + 8 * g) * b.stride + x;
+      if constexpr (G::BMAXV >= 16) {
+        // the region spans multiples of 8 pixels inside the image in both
+        // directions, so every group is whole
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        v[r][0] = v[r][1] = 0u;
-        const int y = b.rg.ay0 + 8 * g + r;
-        if (8 * g + r < 2 * b.hrows) {
-          const uint32_t* p = reinterpret_cast<const uint32_t*>(b.data + (size_t)y * b.stride + x);
-          if (x + 8 <= b.rg.W) {
-            v[r][0] = p[0];
-            v[r][1] = p[1];
-          } else if (x < b.rg.W) {
-            v[r][0] = p[0];
+        for (int r = 0; r < 8; ++r) {
+          const uint32_t* p = reinterpret_cast<const uint32_t*>(row0 + (size_t)r * b.stride);
+          v[r][0] = p[0];
+          v[r][1] = p[1];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          v[r][0] = v[r][1] = 0u;
+          if (8 * g + r < 2 * b.hrows) {
+            const uint32_t* p = reinterpret_cast<const uint32_t*>(row0 + (size_t)r * b.stride);
+            if (x + 8 <= b.rg.W) {
+              v[r][0] = p[0];
+              v[r][1] = p[1];
+            } else if (x < b.rg.W) {
+              v[r][0] = p[0];
+            }
           }
         }
       }

@@ -228,6 +228,45 @@ def test_encode_batch_matches_single(torch_dev, ctx):
         assert_same_stream(recs[offs[k]:offs[k + 1]], mns.encode(im, 16, 4, [300, 200]))
 
 
+def test_plan_replays_match_eager(torch_dev, ctx):
+    """A recorded batch (HIP graph) gives the eager batch's output on every
+    replay, with other device work and synchronisations in between, and
+    follows new contents written into the same image buffers."""
+    rng = np.random.default_rng(9)
+    shapes = [(int(rng.integers(2, 9)) * 32, int(rng.integers(2, 9)) * 32) for _ in range(6)]
+    imgs = [synth.noise_1f(h, w, 300 + k) if k % 2 else synth.piecewise_smooth(h, w, 300 + k)
+            for k, (h, w) in enumerate(shapes)]
+    thr = [300, 200]
+    t_imgs = [dev(torch_dev, im) for im in imgs]
+    out_e, offs_e, n_e = ctx.encode_batch(t_imgs, 16, 4, thr)
+    want = out_e[:n_e].cpu().numpy().tobytes()
+    want_offs = offs_e.cpu().numpy()
+    cap = out_e.shape[0]
+    out = torch_dev.zeros((cap, 16), dtype=torch_dev.uint8, device="cuda")
+    offs = torch_dev.zeros(len(imgs) + 1, dtype=torch_dev.int64, device="cuda")
+    with fb.Plan(ctx, t_imgs, 16, 4, thr, out, offs) as plan:
+        for rep in range(4):
+            log(f"  replay {rep}")
+            out.fill_(0)
+            offs.fill_(0)
+            plan.launch()
+            torch_dev.cuda.synchronize()
+            got_offs = offs.cpu().numpy()
+            np.testing.assert_array_equal(got_offs, want_offs)
+            assert out[:n_e].cpu().numpy().tobytes() == want, f"replay {rep} differs"
+            ctx.encode_batch(t_imgs, 16, 4, thr)               # eager work between replays
+            torch_dev.cuda.synchronize()
+        new = [synth.noise_1f(h, w, 400 + k) for k, (h, w) in enumerate(shapes)]
+        for k, im in enumerate(new):
+            t_imgs[k].copy_(torch_dev.from_numpy(im))
+        plan.launch()
+        torch_dev.cuda.synchronize()
+        offs_h = offs.cpu().numpy()
+        recs = fb.to_records(out[: int(offs_h[-1])])
+        for k, im in enumerate(new):
+            assert_same_stream(recs[offs_h[k]:offs_h[k + 1]], mns.encode(im, 16, 4, thr))
+
+
 # ------------------------------------------------------------------ decode
 @pytest.mark.parametrize("name,b_max,b_min,thr,iters", [
     ("c1", 8, 4, [600], 12),
