@@ -151,11 +151,31 @@ fe::TileShape pick_shape(fe_ctx* ctx, int b_max, int L) {
   return k > 0 ? shapes[0] : fe::TileShape{0, 0};
 }
 
-// Copy `n` table entries, followed by their wg_first values, to the device
-// through the pinned staging buffer (one copy).  Table slots hold
-// fe::ImgDev; the wg_first words start at slot n.
-fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, hipStream_t s) {
-  const size_t slots = n + (n * sizeof(uint32_t) + sizeof(fe::ImgDev) - 1) / sizeof(fe::ImgDev);
+// Host image of the device table: the n ImgDev entries, then their
+// wg_first words, then one word per chunk of kChunkTiles tiles naming the
+// image that holds the chunk's first tile.  Returns the size in ImgDev slots.
+size_t table_words(const fe::ImgDev* src, size_t n, uint64_t tiles, std::vector<fe::ImgDev>& host) {
+  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  const size_t words = n + chunks;
+  const size_t slots = n + (words * sizeof(uint32_t) + sizeof(fe::ImgDev) - 1) / sizeof(fe::ImgDev);
+  host.assign(slots, fe::ImgDev{});
+  memcpy(host.data(), src, n * sizeof(fe::ImgDev));
+  uint32_t* w = reinterpret_cast<uint32_t*>(host.data() + n);
+  for (size_t k = 0; k < n; ++k) w[k] = src[k].wg_first;
+  size_t k = 0;
+  for (size_t c = 0; c < chunks; ++c) {
+    const uint64_t t = (uint64_t)c * fe::kChunkTiles;
+    while (k + 1 < n && src[k + 1].tile_first <= t) ++k;
+    w[n + c] = (uint32_t)k;
+  }
+  return slots;
+}
+
+// Copy the table (see table_words) to the device through the pinned
+// staging buffer (one copy).
+fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, uint64_t tiles, hipStream_t s) {
+  std::vector<fe::ImgDev> host;
+  const size_t slots = table_words(src, n, tiles, host);
   FE_HIP(hipEventSynchronize(ctx->table_ready), "wait for previous table copy");
   if (slots > ctx->h_table_n) {
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
@@ -167,14 +187,18 @@ fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, hipStream_t
   }
   fe_status st = ensure(ctx->d_table, ctx->d_table_n, slots, "device image table");
   if (st != FE_OK) return st;
-  memcpy(ctx->h_table, src, n * sizeof(fe::ImgDev));
-  uint32_t* wf = reinterpret_cast<uint32_t*>(ctx->h_table + n);
-  for (size_t k = 0; k < n; ++k) wf[k] = src[k].wg_first;
+  memcpy(ctx->h_table, host.data(), slots * sizeof(fe::ImgDev));
   FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
          "image table copy");
   FE_HIP(hipEventRecord(ctx->table_ready, s), "table event");
   return FE_OK;
 }
+
+// Device pointers into a table built by table_words.
+inline const uint32_t* table_wg_first(const fe::ImgDev* d, size_t n) {
+  return reinterpret_cast<const uint32_t*>(d + n);
+}
+inline const uint32_t* table_chunk_img(const fe::ImgDev* d, size_t n) { return table_wg_first(d, n) + n; }
 
 // Arguments of a batch encode (fe_encode_batch, fe_plan_create).
 fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* p, const fe_transform* d_out,
@@ -234,7 +258,10 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   fe_status st = build_table(imgs, n_imgs, p, shape, table, tiles, wgs);
   if (st != FE_OK) return st;
   const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
-  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
+  // record slots: one group of NT * cells per workgroup block
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)wgs * (size_t)(shape.gx * shape.gy) * cells,
+                  "record staging")) != FE_OK)
+    return st;
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
@@ -244,12 +271,12 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
     offsets = ctx->offsets;
   }
-  if ((st = upload_table(ctx, table.data(), n_imgs, s)) != FE_OK) return st;
+  if ((st = upload_table(ctx, table.data(), n_imgs, tiles, s)) != FE_OK) return st;
 
   FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, ctx->blocks, s), "prep launch");
   fe::EncodeArgs a{};
   a.imgs = ctx->d_table;
-  a.wg_first = reinterpret_cast<const uint32_t*>(ctx->d_table + n_imgs);
+  a.wg_first = table_wg_first(ctx->d_table, n_imgs);
   a.blocks = ctx->blocks;
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
@@ -263,7 +290,8 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   }
   {
     Timed t(ctx, FE_TIMING_SCATTER, s);
-    FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->chunk_base,
+    FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, table_chunk_img(ctx->d_table, n_imgs), tiles, cells, shape,
+                              ctx->masks, ctx->chunk_sum, ctx->chunk_base,
                               ctx->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, offsets, s),
            "scatter kernel launch");
   }
@@ -332,7 +360,7 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
   im.groups_y = im.tiles_y;
   im.wg_first = 0;
   im.tile_first = 0;
-  if ((st = upload_table(ctx, &im, 1, s)) != FE_OK) return st;
+  if ((st = upload_table(ctx, &im, 1, tiles, s)) != FE_OK) return st;
   FE_HIP(fe::launch_zero_u32(reinterpret_cast<uint32_t*>(ctx->masks), (size_t)tiles * 2, s), "zero masks");
   FE_HIP(fe::fs_planes(pl0, d_img, w, h, stride, ctx->fs_planes, s), "phase planes");
   FE_HIP(fe::fs_level1(w, h, p->b_max, ctx->fs_xy[0], s), "level-1 ranges");
@@ -361,7 +389,9 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
     FE_HIP(hipStreamSynchronize(s), "level");
     R = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
   }
-  FE_HIP(fe::launch_scatter(ctx->d_table, 1, tiles, cells, ctx->masks, ctx->chunk_sum, ctx->chunk_base, ctx->staging,
+  // records sit tile-major (blocks of one tile)
+  FE_HIP(fe::launch_scatter(ctx->d_table, 1, nullptr, tiles, cells, fe::TileShape{1, 1}, ctx->masks, ctx->chunk_sum,
+                            ctx->chunk_base, ctx->staging,
                             reinterpret_cast<uint4*>(d_out), (uint64_t)cap, ctx->offsets, s),
          "scatter launch");
   FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->offsets + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "count");
@@ -744,15 +774,14 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   fe_plan* pl = new fe_plan();
   pl->device = ctx->device;
   pl->n_imgs = n_imgs;
-  // device table: the ImgDev entries followed by their wg_first words
-  const size_t slots = n_imgs + (n_imgs * sizeof(uint32_t) + sizeof(fe::ImgDev) - 1) / sizeof(fe::ImgDev);
-  std::vector<fe::ImgDev> host(slots);
-  memcpy(host.data(), table.data(), n_imgs * sizeof(fe::ImgDev));
-  uint32_t* wf = reinterpret_cast<uint32_t*>(host.data() + n_imgs);
-  for (uint32_t k = 0; k < n_imgs; ++k) wf[k] = table[k].wg_first;
+  // device table: the ImgDev entries, their wg_first words, chunk images
+  std::vector<fe::ImgDev> host;
+  const size_t slots = table_words(table.data(), n_imgs, tiles, host);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_table), slots * sizeof(fe::ImgDev));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->blocks), std::max<size_t>(wgs, 1) * sizeof(fe::BlockDesc));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->staging), std::max<size_t>(tiles * cells, 1) * 16);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&pl->staging),
+                  std::max<size_t>((size_t)wgs * (size_t)(shape.gx * shape.gy) * cells, 1) * 16);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->masks), std::max<size_t>(tiles, 1) * 8);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_sum), std::max<size_t>(chunks, 1) * 4);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_base), (chunks + 1) * 8);
@@ -767,7 +796,7 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   // record the launch sequence once; replays re-read the images in place
   fe::EncodeArgs a{};
   a.imgs = pl->d_table;
-  a.wg_first = reinterpret_cast<const uint32_t*>(pl->d_table + n_imgs);
+  a.wg_first = table_wg_first(pl->d_table, n_imgs);
   a.blocks = pl->blocks;
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
@@ -780,7 +809,8 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     hipError_t le = fe::launch_block_prep(pl->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, pl->blocks, pl->capture);
     if (le == hipSuccess) le = fe::launch_mns_tiles(bmax, L, shape, a, pl->capture);
     if (le == hipSuccess)
-      le = fe::launch_scatter(pl->d_table, n_imgs, tiles, cells, pl->masks, pl->chunk_sum, pl->chunk_base,
+      le = fe::launch_scatter(pl->d_table, n_imgs, table_chunk_img(pl->d_table, n_imgs), tiles, cells, shape,
+                              pl->masks, pl->chunk_sum, pl->chunk_base,
                               pl->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, d_offsets, pl->capture);
     e = hipStreamEndCapture(pl->capture, &pl->graph);
     if (le != hipSuccess) e = le;

@@ -26,7 +26,7 @@ struct BlockDesc {
   uint32_t stride;      // image row pitch (bytes)
   uint32_t wh;          // (width - 1) | (height - 1) << 16
   uint32_t t0;          // first tile of the block: tx0 | ty0 << 16
-  uint32_t pad;
+  uint32_t sblk;        // record-slot block (see EncodeArgs::staging)
 };
 
 // Per-call encoder constants (passed by value).
@@ -39,7 +39,11 @@ struct EncodeArgs {
   uint32_t phase2;     // run Technique 1
   uint32_t pad;
   uint32_t thr[4];     // MSE thresholds of levels 1..L-1
-  uint4* staging;      // tile-major record slots: tile * cells + morton cell
+  // Record slots, one group of NT * cells per workgroup block (NT tiles),
+  // cell-major inside it: the record of Morton cell c of the block's tile t
+  // is at sblk * NT * cells + c * NT + t, so the one-record tiles of a block
+  // (cell 0) lie side by side.
+  uint4* staging;
   uint64_t* masks;     // per tile: bit c set when cell c holds a record
 };
 
@@ -69,9 +73,14 @@ hipError_t launch_block_prep(const ImgDev* imgs, uint32_t n_imgs, uint32_t n_wg,
 // records from staging into stream order; writes per-image offsets and the
 // total (offsets[n_imgs]).  chunk_sum needs ceil(tiles / kChunkTiles)
 // entries, chunk_base one more.
-hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, uint64_t total_tiles, int cells,
-                          const uint64_t* masks, uint32_t* chunk_sum, uint64_t* chunk_base,
-                          const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
+// Records are read from the block-grouped, cell-major slots written by the
+// encode kernel for tile shape `shape`; an image's blocks are numbered from
+// its wg_first in row-major block order.
+// chunk_img[c] is the image holding tile c * kChunkTiles (NULL when there
+// is one image).
+hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* chunk_img, uint64_t total_tiles,
+                          int cells, TileShape shape, const uint64_t* masks, uint32_t* chunk_sum,
+                          uint64_t* chunk_base, const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
                           hipStream_t stream);
 
 hipError_t launch_downsample(const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,

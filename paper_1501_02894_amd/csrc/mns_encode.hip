@@ -115,6 +115,7 @@ struct BlockGeo {
   int gx, gy;            // tiles of the block inside the image
   int n8, hrows;         // region: 8-pixel column groups, row pairs
   int tx_end, ty_end;    // end of the tile block (pixels)
+  uint32_t sblk;         // record-slot block
 };
 
 template <int BMAX, int GX, int GY>
@@ -143,6 +144,7 @@ __device__ __forceinline__ BlockGeo block_geo(const BlockDesc& d) {
   b.ty_end = b.rg.Y0 + b.gy * BMAX;
   b.data = d.data;
   b.stride = d.stride;
+  b.sblk = d.sblk;
   return b;
 }
 
@@ -271,6 +273,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   const uint32_t* s_h0 = sm.h0;
   const uint32_t* s_h0t = sm.h0t;
   unsigned long long* s_mask = sm.mask;
+  const uint64_t slot0 = (uint64_t)bg.sblk * (uint64_t)(G::NT * G::CELLS);   // the block's record slots
   const int wave = tid >> 6, lane = tid & 63;
   const int t_first = wave * G::NTW;
   uint32_t* w_meta0 = sm.meta[wave][0];
@@ -366,7 +369,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
               const int pdx = clampi(PX - PB / 2, 0, rg.W - 2 * PB);
               const int pdy = clampi(PY - PB / 2, 0, rg.H - 2 * PB);
               const int cell = morton(pmeta);
-              a.staging[tile_global<G::LOG_GX>(pmeta, rg) * G::CELLS + cell] =
+              a.staging[slot0 + (uint32_t)(cell * G::NT) + ((pmeta >> 16) & 0xffu)] =
                   make_record(PX, PY, pdx, pdy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
               atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
             }
@@ -381,7 +384,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
             const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
             const int cell = morton(meta);
-            a.staging[tile_global<G::LOG_GX>(meta, rg) * G::CELLS + cell] =
+            a.staging[slot0 + (uint32_t)(cell * G::NT) + ((meta >> 16) & 0xffu)] =
                 make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                             (int)(fit & 0xffu), 0, 0, 0);
             atomicOr(&s_mask[meta >> 16], 1ull << cell);
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(256) void block_prep_kernel(const ImgDev* imgs, uin
   d.stride = im.stride;
   d.wh = (im.width - 1u) | ((im.height - 1u) << 16);
   d.t0 = tx0 | (ty0 << 16);
-  d.pad = 0;
+  d.sblk = wg;
   blocks[wg] = d;
 }
 
@@ -516,25 +519,56 @@ __global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* chunk_
 // scans its tiles' counts, then copies its contiguous output range with one
 // record per lane (coalesced writes), locating each record's tile by binary
 // search over the tile bases.
+// Images a chunk of kChunkTiles tiles can touch: every image has at least
+// 2 x 2 top tiles.
+constexpr int kChunkImgs = kChunkTiles / 4 + 1;
+
 __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
-                                                     uint64_t total_tiles, int cells,
-                                                     const uint64_t* masks, const uint64_t* chunk_base,
-                                                     const uint4* staging, uint4* out, uint64_t cap,
-                                                     uint64_t* offsets) {
+                                                     const uint32_t* chunk_img, uint64_t total_tiles, int cells,
+                                                     int gx, int gy, const uint64_t* masks,
+                                                     const uint64_t* chunk_base, const uint4* staging, uint4* out,
+                                                     uint64_t cap, uint64_t* offsets) {
   __shared__ uint32_t s_wsum[4];
   __shared__ uint32_t s_tbase[kChunkTiles + 1];
   __shared__ unsigned long long s_mk[kChunkTiles];
+  __shared__ unsigned long long s_slot[kChunkTiles];   // slot of cell 0 of each tile
+  __shared__ unsigned long long s_tf[kChunkImgs];      // the chunk's images: first tile,
+  __shared__ uint32_t s_tx[kChunkImgs], s_gx[kChunkImgs], s_wf[kChunkImgs];   // tiles / blocks per row, first block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t c0 = (uint64_t)blockIdx.x * kChunkTiles;
   const unsigned long long base = chunk_base[blockIdx.x];
+  const uint32_t k0 = chunk_img ? chunk_img[blockIdx.x] : 0u;
+  const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
+  if (tid < nk) {
+    const ImgDev& im = imgs[k0 + tid];
+    s_tf[tid] = im.tile_first;
+    s_tx[tid] = im.tiles_x;
+    s_gx[tid] = im.groups_x;
+    s_wf[tid] = im.wg_first;
+  }
+  __syncthreads();
+  const int nt = gx * gy;
   constexpr int PER = kChunkTiles / 256;
   uint32_t cnt[PER];
   uint32_t tsum = 0;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const uint64_t tile = c0 + (uint64_t)tid * PER + j;
-    const unsigned long long m = tile < total_tiles ? masks[tile] : 0ull;
+    unsigned long long m = 0ull, slot = 0ull;
+    if (tile < total_tiles) {
+      m = masks[tile];
+      // the tile's image: the last of the chunk's images starting at or before it
+      int k = 0;
+      while (k + 1 < nk && s_tf[k + 1] <= tile) ++k;
+      const uint32_t local = (uint32_t)(tile - s_tf[k]);
+      const uint32_t ty = local / s_tx[k], tx = local - ty * s_tx[k];
+      const uint32_t by = ty / (uint32_t)gy, bx = tx / (uint32_t)gx;
+      const uint64_t blk = (uint64_t)s_wf[k] + (uint64_t)by * s_gx[k] + bx;
+      const uint32_t t = (ty - by * (uint32_t)gy) * (uint32_t)gx + (tx - bx * (uint32_t)gx);
+      slot = blk * (uint64_t)nt * (uint64_t)cells + t;
+    }
     s_mk[tid * PER + j] = m;
+    s_slot[tid * PER + j] = slot;
     cnt[j] = (uint32_t)__popcll(m);
     tsum += cnt[j];
   }
@@ -561,17 +595,33 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   }
   if (tid == 0) s_tbase[kChunkTiles] = total;
   __syncthreads();
-  for (uint32_t r = tid; r < total; r += 256) {
-    int lo = 0, hi = kChunkTiles - 1;      // last tile with base <= r
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_tbase[mid] <= r) lo = mid; else hi = mid - 1;
+  // records r = r0 + tid + 256 u (consecutive lanes, consecutive outputs):
+  // the four records' slots are located first (LDS only), then all four
+  // loads are issued unconditionally (index clamped into range), then the
+  // stores, so that the loads overlap
+  constexpr int U = 4;
+  for (uint32_t r0 = 0; r0 < total; r0 += 256 * U) {
+    uint64_t sl[U];
+    unsigned long long o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t r = r0 + (uint32_t)(tid + 256 * u);
+      const uint32_t rr = r < total ? r : total - 1u;
+      int lo = 0, hi = kChunkTiles - 1;      // last tile with base <= rr
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_tbase[mid] <= rr) lo = mid; else hi = mid - 1;
+      }
+      unsigned long long m = s_mk[lo];
+      for (uint32_t k = rr - s_tbase[lo]; k > 0; --k) m &= m - 1;
+      sl[u] = s_slot[lo] + (uint64_t)__builtin_ctzll(m) * (uint64_t)nt;
+      o[u] = r < total ? base + r : ~0ull;
     }
-    unsigned long long m = s_mk[lo];
-    for (uint32_t k = r - s_tbase[lo]; k > 0; --k) m &= m - 1;
-    const int cell = __builtin_ctzll(m);
-    const unsigned long long o = base + r;
-    if (o < cap) out[o] = staging[(c0 + lo) * (uint64_t)cells + cell];
+    const uint4 v0 = staging[sl[0]], v1 = staging[sl[1]], v2 = staging[sl[2]], v3 = staging[sl[3]];
+    if (o[0] < cap) out[o[0]] = v0;
+    if (o[1] < cap) out[o[1]] = v1;
+    if (o[2] < cap) out[o[2]] = v2;
+    if (o[3] < cap) out[o[3]] = v3;
   }
   for (uint32_t k = tid; k < n_imgs; k += 256) {
     const uint64_t tf = imgs[k].tile_first;
@@ -632,14 +682,15 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, uint64_t total_tiles, int cells,
-                          const uint64_t* masks, uint32_t* chunk_sum, uint64_t* chunk_base, const uint4* staging,
-                          uint4* out, uint64_t cap, uint64_t* offsets, hipStream_t s) {
+hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* chunk_img, uint64_t total_tiles,
+                          int cells, TileShape shape, const uint64_t* masks, uint32_t* chunk_sum,
+                          uint64_t* chunk_base, const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
+                          hipStream_t s) {
   const unsigned grid = (unsigned)((total_tiles + kChunkTiles - 1) / kChunkTiles);
   hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(kChunkTiles), 0, s, masks, total_tiles, chunk_sum);
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, chunk_sum, grid, chunk_base);
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, total_tiles, cells, masks,
-                     chunk_base, staging, out, cap, offsets);
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, cells,
+                     shape.gx, shape.gy, masks, chunk_base, staging, out, cap, offsets);
   return hipGetLastError();
 }
 

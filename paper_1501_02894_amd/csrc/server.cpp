@@ -127,7 +127,8 @@ struct fe_server {
   Arena dev_arena, tile_arena, host_arena;
   std::vector<int> free_slots;
   uint32_t max_slots = 0, step_blocks = 0;
-  fe::ImgDev* d_one = nullptr;           // one-image table (tile_first 0) for ordering
+  fe::ImgDev* d_imgs = nullptr;          // per admission slot: the request's image entry
+  fe::ImgDev* h_imgs = nullptr;          // its pinned source
   fe::BlockDesc* h_desc[2] = {nullptr, nullptr};
   fe::BlockDesc* d_desc[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
@@ -157,6 +158,12 @@ size_t byte_footprint(const Request* r) {
 }
 
 size_t host_out_bytes(const Request* r) { return r->cap * 16 + 16; }
+
+// Tile slots of a request: its workgroup blocks, each a full GX x GY group
+// (record slots are laid out per block).
+size_t slot_tiles(const fe_server* s, const Request* r) {
+  return (size_t)r->blocks * (size_t)(s->shape.gx * s->shape.gy);
+}
 
 void release_request(fe_server* s, Request* r) {
   if (r->dev_len) s->dev_arena.release(r->dev_off, r->dev_len);
@@ -190,14 +197,15 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
     const size_t need = byte_footprint(r);
     const size_t off = s->dev_arena.alloc(need);
     if (off == SIZE_MAX) break;   // head of the queue waits for memory
-    const size_t tb = s->tile_arena.alloc(r->tiles);
+    const size_t tlen = slot_tiles(s, r);
+    const size_t tb = s->tile_arena.alloc(tlen);
     if (tb == SIZE_MAX) {
       s->dev_arena.release(off, need);
       break;
     }
     const size_t hout = s->host_arena.alloc(host_out_bytes(r));
     if (hout == SIZE_MAX) {
-      s->tile_arena.release(tb, r->tiles);
+      s->tile_arena.release(tb, tlen);
       s->dev_arena.release(off, need);
       break;
     }
@@ -210,7 +218,7 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
     r->hout_off = hout;
     r->hout_len = host_out_bytes(r);
     r->tile_base = tb;
-    r->tile_len = r->tiles;
+    r->tile_len = tlen;
     r->slot = s->free_slots.back();
     s->free_slots.pop_back();
     s->active.push_back(r);       // still Queued: run_step skips it
@@ -222,8 +230,22 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
   std::vector<char> ok(adm.size(), 0);
   for (size_t k = 0; k < adm.size(); ++k) {
     Request* r = adm[k];
-    hipError_t e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
-                                  hipMemcpyHostToDevice, s->copy);
+    // the request's image entry for its ordering kernel (blocks numbered
+    // from 0 within the request's slot range)
+    fe::ImgDev& im = s->h_imgs[r->slot];
+    im = fe::ImgDev{};
+    im.data = s->dev_base + r->img_off;
+    im.width = r->w;
+    im.height = r->h;
+    im.stride = r->pitch;
+    im.tiles_x = r->tiles_x;
+    im.tiles_y = r->tiles_y;
+    im.groups_x = r->groups_x;
+    im.groups_y = (uint32_t)(r->blocks / r->groups_x);
+    hipError_t e = hipMemcpyAsync(s->d_imgs + r->slot, &im, sizeof im, hipMemcpyHostToDevice, s->copy);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
+                         hipMemcpyHostToDevice, s->copy);
     if (e == hipSuccess)
       e = fe::launch_zero_u32(reinterpret_cast<uint32_t*>(s->masks + r->tile_base), (size_t)r->tiles * 2, s->copy);
     if (e == hipSuccess) e = hipEventRecord(s->ev_copied[r->slot], s->copy);
@@ -268,7 +290,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
       d.stride = r->pitch;
       d.wh = (r->w - 1u) | ((r->h - 1u) << 16);
       d.t0 = tx0 | (ty0 << 16);
-      d.pad = 0;
+      d.sblk = (uint32_t)(r->tile_base / (size_t)(s->shape.gx * s->shape.gy) + b);
     }
     if (r->next_block == r->blocks) finishing.push_back(r);
   }
@@ -293,7 +315,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     if (e != hipSuccess) break;
     // records and offsets go straight to the pinned host output
     uint8_t* hout = s->host_base + r->hout_off;
-    e = fe::launch_scatter(s->d_one, 1, r->tiles, s->cells, s->masks + r->tile_base,
+    e = fe::launch_scatter(s->d_imgs + r->slot, 1, nullptr, r->tiles, s->cells, s->shape, s->masks + r->tile_base,
                            reinterpret_cast<uint32_t*>(s->dev_base + r->csum_off),
                            reinterpret_cast<uint64_t*>(s->dev_base + r->cbase_off),
                            s->staging + r->tile_base * (size_t)s->cells, reinterpret_cast<uint4*>(hout), r->cap,
@@ -409,7 +431,9 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
             hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * s->cells * 16) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&s->d_one), sizeof(fe::ImgDev)) == hipSuccess;
+            hipMalloc(reinterpret_cast<void**>(&s->d_imgs), (size_t)max_slots * sizeof(fe::ImgDev)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->h_imgs), (size_t)max_slots * sizeof(fe::ImgDev),
+                          hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
     ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc),
                        hipHostMallocDefault) == hipSuccess &&
@@ -421,16 +445,13 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   for (uint32_t k = 0; ok && k < max_slots; ++k)
     ok = hipEventCreateWithFlags(&s->ev_copied[k], hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&s->ev_done[k], hipEventDisableTiming) == hipSuccess;
-  if (ok) {
-    fe::ImgDev one{};
-    ok = hipMemcpy(s->d_one, &one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
-  }
   if (!ok) {
     fe_server_destroy(s);
     return fe::fail(FE_ERR_OOM, "server allocation failed");
   }
   s->dev_arena.reset(byte_budget, 256);
-  s->tile_arena.reset(tiles_cap, 16);
+  // tile slots are handed out in whole blocks of the tile shape
+  s->tile_arena.reset(tiles_cap, (size_t)(s->shape.gx * s->shape.gy));
   s->host_arena.reset(host_budget, 256);
   for (int k = (int)max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->worker = std::thread(worker_main, s);
@@ -462,7 +483,8 @@ void fe_server_destroy(fe_server* s) {
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : s->ev_done)
     if (ev) (void)hipEventDestroy(ev);
-  if (s->d_one) (void)hipFree(s->d_one);
+  if (s->d_imgs) (void)hipFree(s->d_imgs);
+  if (s->h_imgs) (void)hipHostFree(s->h_imgs);
   if (s->dev_base) (void)hipFree(s->dev_base);
   if (s->staging) (void)hipFree(s->staging);
   if (s->masks) (void)hipFree(s->masks);
@@ -490,7 +512,7 @@ fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint3
   r->cap = fe_max_transforms(w, h, s->params.b_min);
   r->chunks = (size_t)((r->tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
   std::unique_lock<std::mutex> lk(s->mu);
-  if (byte_footprint(r) > s->dev_arena.size() || r->tiles > s->tile_arena.size()) {
+  if (byte_footprint(r) > s->dev_arena.size() || slot_tiles(s, r) > s->tile_arena.size()) {
     delete r;
     return fe::fail(FE_ERR_OOM, "request is larger than the server's device budget");
   }
