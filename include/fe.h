@@ -171,7 +171,13 @@ size_t fe_max_transforms(uint32_t width, uint32_t height, uint32_t b_min);
 /*
  * Open a context on HIP device `device` (must be gfx950).  FE_ERR_DEVICE
  * when there is no such device.  The context owns scratch memory that grows
- * with the largest request seen and is freed by fe_destroy.
+ * with the largest request seen and is freed by fe_destroy.  Calls on one
+ * context share that scratch: issue them from one host thread; calls on
+ * different streams are ordered through it (a later call waits on the device
+ * for the image table and block descriptors an earlier one wrote) but their
+ * kernels must not overlap.  A batch with the same image table as the
+ * previous call (same images, sizes and tile shape) reuses the table and
+ * block descriptors already on the device.
  */
 fe_status fe_create(int device, fe_ctx** out);
 void fe_destroy(fe_ctx* ctx);
@@ -237,9 +243,10 @@ fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_i
  * fe_encode_batch writes them; the caller reads d_offsets[n_imgs] and checks
  * it against cap.  Launches on one plan must not overlap; fe_plan_destroy
  * waits for the device.  The plan keeps the context's tile shape at
- * creation and uses the context for kernel timing (fe_timing_*): while
- * timing is enabled each launch's encode and ordering kernels are timed as
- * in eager calls.  The context must outlive the plan.  For callers that encode the same set of buffers repeatedly
+ * creation.  If timing (fe_timing_enable) is on when the plan is created,
+ * the graph also holds event nodes, and each launch made while timing is on
+ * times its encode and ordering kernels into the context as eager calls
+ * do.  The context must outlive the plan.  For callers that encode the same set of buffers repeatedly
  * (video frames, a fixed input ring).
  */
 typedef struct fe_plan fe_plan;

@@ -15,6 +15,12 @@ struct fe_ctx {
   hipEvent_t table_ready = nullptr;   // last copy out of h_table finished
   fe::ImgDev* h_table = nullptr;      // pinned staging of the image table
   size_t h_table_n = 0;
+  size_t table_slots = 0;             // size of the table on the device (0: none)
+  uint64_t table_gen = 0;             // bumped whenever the device table changes
+  bool blocks_valid = false;          // block descriptors built from ...
+  uint64_t blocks_gen = 0;            // ... this table generation,
+  int blocks_key[3] = {0, 0, 0};      // ... b_max and tile shape
+  hipEvent_t blocks_ready = nullptr;  // recorded after the last block-descriptor build
   uint64_t* h_scalars = nullptr;      // pinned read-back words
   fe::ImgDev* d_table = nullptr;
   size_t d_table_n = 0;
@@ -172,10 +178,17 @@ size_t table_words(const fe::ImgDev* src, size_t n, uint64_t tiles, std::vector<
 }
 
 // Copy the table (see table_words) to the device through the pinned
-// staging buffer (one copy).
+// staging buffer (one copy).  A table equal to the one already on the
+// device (the pinned buffer still holds it) is not copied again.
 fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, uint64_t tiles, hipStream_t s) {
   std::vector<fe::ImgDev> host;
   const size_t slots = table_words(src, n, tiles, host);
+  if (ctx->table_slots == slots && ctx->d_table && ctx->h_table &&
+      memcmp(ctx->h_table, host.data(), slots * sizeof(fe::ImgDev)) == 0) {
+    // already on the device; order this stream after its copy
+    FE_HIP(hipStreamWaitEvent(s, ctx->table_ready, 0), "wait for table copy");
+    return FE_OK;
+  }
   FE_HIP(hipEventSynchronize(ctx->table_ready), "wait for previous table copy");
   if (slots > ctx->h_table_n) {
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
@@ -185,12 +198,15 @@ fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, uint64_t ti
            "pinned image table");
     ctx->h_table_n = slots;
   }
+  ctx->table_slots = 0;   // invalid until the copy is enqueued
+  ++ctx->table_gen;
   fe_status st = ensure(ctx->d_table, ctx->d_table_n, slots, "device image table");
   if (st != FE_OK) return st;
   memcpy(ctx->h_table, host.data(), slots * sizeof(fe::ImgDev));
   FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
          "image table copy");
   FE_HIP(hipEventRecord(ctx->table_ready, s), "table event");
+  ctx->table_slots = slots;
   return FE_OK;
 }
 
@@ -265,7 +281,9 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
   if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
+  const size_t blocks_cap = ctx->blocks_n;
   if ((st = ensure(ctx->blocks, ctx->blocks_n, (size_t)wgs, "block descriptors")) != FE_OK) return st;
+  if (ctx->blocks_n != blocks_cap) ctx->blocks_valid = false;   // reallocated
   uint64_t* offsets = d_offsets;
   if (!offsets) {
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
@@ -273,7 +291,22 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   }
   if ((st = upload_table(ctx, table.data(), n_imgs, tiles, s)) != FE_OK) return st;
 
-  FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, ctx->blocks, s), "prep launch");
+  // block descriptors: rebuilt unless they were built from this very table
+  // and shape (the buffer is only written here)
+  if (!ctx->blocks_valid || ctx->blocks_gen != ctx->table_gen || ctx->blocks_key[0] != bmax ||
+      ctx->blocks_key[1] != shape.gx || ctx->blocks_key[2] != shape.gy) {
+    ctx->blocks_valid = false;
+    FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, ctx->blocks, s),
+           "prep launch");
+    FE_HIP(hipEventRecord(ctx->blocks_ready, s), "blocks event");
+    ctx->blocks_valid = true;
+    ctx->blocks_gen = ctx->table_gen;
+    ctx->blocks_key[0] = bmax;
+    ctx->blocks_key[1] = shape.gx;
+    ctx->blocks_key[2] = shape.gy;
+  } else {
+    FE_HIP(hipStreamWaitEvent(s, ctx->blocks_ready, 0), "wait for block descriptors");
+  }
   fe::EncodeArgs a{};
   a.imgs = ctx->d_table;
   a.wg_first = table_wg_first(ctx->d_table, n_imgs);
@@ -421,6 +454,7 @@ fe_status fe_create(int device, fe_ctx** out) {
   fe_ctx* c = new fe_ctx();
   c->device = device;
   hipError_t e1 = hipEventCreateWithFlags(&c->table_ready, hipEventDisableTiming);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&c->blocks_ready, hipEventDisableTiming);
   hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&c->h_scalars), 64, hipHostMallocDefault);
   hipError_t e3 = hipMalloc(reinterpret_cast<void**>(&c->flags), 64);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -436,6 +470,7 @@ void fe_destroy(fe_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
   if (c->table_ready) (void)hipEventDestroy(c->table_ready);
+  if (c->blocks_ready) (void)hipEventDestroy(c->blocks_ready);
   if (c->h_table) (void)hipHostFree(c->h_table);
   if (c->h_scalars) (void)hipHostFree(c->h_scalars);
   (void)hipFree(c->d_table);
@@ -819,11 +854,11 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     fe_plan_destroy(pl);
     return hip_fail(e, "plan capture");
   }
-  // The capture is a chain: prep, encode, then the ordering kernels.  A
-  // copy of it gets event-record nodes before and after the encode kernel
-  // and after the last ordering kernel (for timing); if that fails, the
-  // plain chain is used and launches are not timed.
-  pl->timed = add_timing_nodes(pl);
+  // The capture is a chain: prep, encode, then the ordering kernels.  If
+  // timing is on, a copy of it gets event-record nodes before and after the
+  // encode kernel and after the last ordering kernel; if that fails, or
+  // timing is off, the plain chain is used and launches are not timed.
+  pl->timed = ctx->timing && add_timing_nodes(pl);
   if (!pl->timed) {
     e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {

@@ -226,6 +226,16 @@ def test_encode_batch_matches_single(torch_dev, ctx):
     recs = fb.to_records(out[:n])
     for k, im in enumerate(imgs):
         assert_same_stream(recs[offs[k]:offs[k + 1]], mns.encode(im, 16, 4, [300, 200]))
+    # the same batch again reuses the device table and block descriptors;
+    # after another call with a different table it is rebuilt
+    first = out[:n].cpu().numpy().tobytes()
+    for other in (None, [t_imgs[0]], None):
+        if other is not None:
+            ctx.encode_batch(other, 16, 4, [300, 200])
+        out2, offs2, n2 = ctx.encode_batch(t_imgs, 16, 4, [300, 200])
+        torch_dev.cuda.synchronize()
+        assert n2 == n and out2[:n2].cpu().numpy().tobytes() == first
+        np.testing.assert_array_equal(offs2.cpu().numpy(), offs)
 
 
 def test_plan_replays_match_eager(torch_dev, ctx):
@@ -265,6 +275,24 @@ def test_plan_replays_match_eager(torch_dev, ctx):
         recs = fb.to_records(out[: int(offs_h[-1])])
         for k, im in enumerate(new):
             assert_same_stream(recs[offs_h[k]:offs_h[k + 1]], mns.encode(im, 16, 4, thr))
+    # a plan created while timing is on times each launch's kernels
+    fb.fe_timing_read(ctx.handle)
+    fb.fe_timing_enable(ctx.handle, True)
+    try:
+        with fb.Plan(ctx, t_imgs, 16, 4, thr, out, offs) as plan:
+            for _ in range(3):
+                plan.launch()
+            torch_dev.cuda.synchronize()
+            ms, cnt = fb.fe_timing_read(ctx.handle)
+            assert cnt[fb.FE_TIMING_ENCODE] == 3 and cnt[fb.FE_TIMING_SCATTER] == 3
+            assert ms[fb.FE_TIMING_ENCODE] > 0 and ms[fb.FE_TIMING_SCATTER] > 0
+            fb.fe_timing_enable(ctx.handle, False)
+            plan.launch()                                      # untimed launch after timing is off
+            torch_dev.cuda.synchronize()
+            assert out[: int(offs.cpu().numpy()[-1])].cpu().numpy().tobytes() == recs.tobytes()
+            assert fb.fe_timing_read(ctx.handle)[1][fb.FE_TIMING_ENCODE] == 0
+    finally:
+        fb.fe_timing_enable(ctx.handle, False)
 
 
 # ------------------------------------------------------------------ decode
