@@ -148,6 +148,10 @@ __device__ __forceinline__ BlockGeo block_geo(const BlockDesc& d) {
   return b;
 }
 
+// Image words read through the global address space (global_load rather
+// than flat_load, which would also occupy the LDS counter).
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+
 // Region staging.  A group is 8 x 8 pixels of the region (column group c8,
 // rows 8 g .. 8 g + 7), i.e. a 4 x 4 block of H0; lane `tid` owns groups
 // tid + 256 * it.  H0 is written as dwords, and its transpose as dwords
@@ -172,7 +176,7 @@ struct Stage {
         // directions, so every group is whole
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-          const uint32_t* p = reinterpret_cast<const uint32_t*>(row0 + (size_t)r * b.stride);
+          const gu32* p = (const gu32*)(row0 + (size_t)r * b.stride);
           v[r][0] = p[0];
           v[r][1] = p[1];
         }
@@ -181,7 +185,7 @@ struct Stage {
         for (int r = 0; r < 8; ++r) {
           v[r][0] = v[r][1] = 0u;
           if (8 * g + r < 2 * b.hrows) {
-            const uint32_t* p = reinterpret_cast<const uint32_t*>(row0 + (size_t)r * b.stride);
+            const gu32* p = (const gu32*)(row0 + (size_t)r * b.stride);
             if (x + 8 <= b.rg.W) {
               v[r][0] = p[0];
               v[r][1] = p[1];
