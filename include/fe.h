@@ -336,6 +336,11 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  * FE_ERR_INVALID as fe_validate.  Requests are admitted in arrival order
  * when their device footprint fits.
  *
+ * fe_server_submit_pinned queues an image that already lies in pinned
+ * host memory (hipHostMalloc or equivalent; FE_ERR_INVALID otherwise) and
+ * copies it to the device straight from there, with no host-side copy: the
+ * caller must keep h_img unchanged until the request is done.
+ *
  * fe_server_poll: *done = 0 while the request runs.  When done, *n is the
  * stream length and *latency_ms the time from submit to the records being
  * in host memory; if h_out is not NULL the stream is copied there (cap >=
@@ -359,6 +364,8 @@ fe_status fe_server_create(int device, const fe_params* params, size_t hbm_budge
                            uint32_t max_slots, uint32_t step_blocks, fe_server** out);
 fe_status fe_server_submit(fe_server* server, const uint8_t* h_img, uint32_t width, uint32_t height,
                            uint32_t stride, uint64_t* req);
+fe_status fe_server_submit_pinned(fe_server* server, const uint8_t* h_img, uint32_t width, uint32_t height,
+                                  uint32_t stride, uint64_t* req);
 fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, size_t cap, size_t* n,
                          int* done, double* latency_ms);
 fe_status fe_server_wait(fe_server* server, uint32_t timeout_us, uint64_t* req);

@@ -79,6 +79,7 @@ _SIGNATURES = {
     "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
                                         ctypes.POINTER(_VP)]),
     "fe_server_submit": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_submit_pinned": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_uint64)]),
     "fe_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _SZ, ctypes.POINTER(_SZ), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_double)]),
     "fe_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
@@ -372,6 +373,15 @@ def fe_server_submit(server: int, img: np.ndarray) -> int:
     return req.value
 
 
+def fe_server_submit_pinned(server: int, img) -> int:
+    """Submit a 2-D uint8 torch tensor in pinned host memory (no host copy;
+    keep it unchanged until the request is done)."""
+    H, W = img.shape
+    req = ctypes.c_uint64(0)
+    _check(load().fe_server_submit_pinned(server, int(img.data_ptr()), W, H, img.stride(0), ctypes.byref(req)))
+    return req.value
+
+
 def fe_server_poll(server: int, req: int, fetch: bool = True):
     """Returns (done, records or None, latency_ms)."""
     lib = load()
@@ -423,6 +433,9 @@ class Server:
 
     def submit(self, img):
         return fe_server_submit(self.handle, img)
+
+    def submit_pinned(self, img):
+        return fe_server_submit_pinned(self.handle, img)
 
     def poll(self, req, fetch=True):
         return fe_server_poll(self.handle, req, fetch)

@@ -527,6 +527,10 @@ __global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* chunk_
 // 2 x 2 top tiles.
 constexpr int kChunkImgs = kChunkTiles / 4 + 1;
 
+// Up to this many chunks the ordering runs as one kernel whose workgroups
+// count the records before their chunk themselves (at most 16 k masks each).
+constexpr unsigned kSmallChunks = 64;
+
 __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
                                                      const uint32_t* chunk_img, uint64_t total_tiles, int cells,
                                                      int gx, int gy, const uint64_t* masks,
@@ -538,9 +542,22 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   __shared__ unsigned long long s_slot[kChunkTiles];   // slot of cell 0 of each tile
   __shared__ unsigned long long s_tf[kChunkImgs];      // the chunk's images: first tile,
   __shared__ uint32_t s_tx[kChunkImgs], s_gx[kChunkImgs], s_wf[kChunkImgs];   // tiles / blocks per row, first block
+  __shared__ unsigned long long s_red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t c0 = (uint64_t)blockIdx.x * kChunkTiles;
-  const unsigned long long base = chunk_base[blockIdx.x];
+  unsigned long long base;
+  if (chunk_base) {
+    base = chunk_base[blockIdx.x];
+  } else {
+    // few chunks: the records of all earlier tiles, counted here
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)tid; i < c0; i += 256) acc += (unsigned long long)__popcll(masks[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s_red[wave] = acc;
+    __syncthreads();
+    base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+  }
   const uint32_t k0 = chunk_img ? chunk_img[blockIdx.x] : 0u;
   const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
   if (tid < nk) {
@@ -691,6 +708,12 @@ hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* c
                           uint64_t* chunk_base, const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
                           hipStream_t s) {
   const unsigned grid = (unsigned)((total_tiles + kChunkTiles - 1) / kChunkTiles);
+  if (grid <= kSmallChunks) {
+    // one kernel: each chunk counts the records before it itself
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, cells,
+                       shape.gx, shape.gy, masks, (const uint64_t*)nullptr, staging, out, cap, offsets);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(kChunkTiles), 0, s, masks, total_tiles, chunk_sum);
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, chunk_sum, grid, chunk_base);
   hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, cells,

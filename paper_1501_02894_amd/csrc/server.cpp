@@ -100,6 +100,8 @@ struct Request {
   size_t cap = 0;                        // device output capacity (transforms)
   size_t chunks = 0;
   size_t hin_off = 0, hin_len = 0;       // pinned host input copy
+  const uint8_t* hsrc = nullptr;         // or the caller's pinned image (zero-copy submit)
+  uint32_t hstride = 0;                  // its row pitch
   size_t dev_off = 0, dev_len = 0;       // byte arena region
   size_t img_off = 0, csum_off = 0, cbase_off = 0;
   size_t tile_base = 0, tile_len = 0;    // tile arena range
@@ -127,8 +129,6 @@ struct fe_server {
   Arena dev_arena, tile_arena, host_arena;
   std::vector<int> free_slots;
   uint32_t max_slots = 0, step_blocks = 0;
-  fe::ImgDev* d_imgs = nullptr;          // per admission slot: the request's image entry
-  fe::ImgDev* h_imgs = nullptr;          // its pinned source
   fe::BlockDesc* h_desc[2] = {nullptr, nullptr};
   fe::BlockDesc* d_desc[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
@@ -230,24 +230,11 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
   std::vector<char> ok(adm.size(), 0);
   for (size_t k = 0; k < adm.size(); ++k) {
     Request* r = adm[k];
-    // the request's image entry for its ordering kernel (blocks numbered
-    // from 0 within the request's slot range)
-    fe::ImgDev& im = s->h_imgs[r->slot];
-    im = fe::ImgDev{};
-    im.data = s->dev_base + r->img_off;
-    im.width = r->w;
-    im.height = r->h;
-    im.stride = r->pitch;
-    im.tiles_x = r->tiles_x;
-    im.tiles_y = r->tiles_y;
-    im.groups_x = r->groups_x;
-    im.groups_y = (uint32_t)(r->blocks / r->groups_x);
-    hipError_t e = hipMemcpyAsync(s->d_imgs + r->slot, &im, sizeof im, hipMemcpyHostToDevice, s->copy);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off, (size_t)r->pitch * r->h,
-                         hipMemcpyHostToDevice, s->copy);
-    if (e == hipSuccess)
-      e = fe::launch_zero_u32(reinterpret_cast<uint32_t*>(s->masks + r->tile_base), (size_t)r->tiles * 2, s->copy);
+    // the image (the encode kernel writes every tile's mask whole)
+    hipError_t e = r->hsrc ? hipMemcpy2DAsync(s->dev_base + r->img_off, r->pitch, r->hsrc, r->hstride, r->w, r->h,
+                                              hipMemcpyHostToDevice, s->copy)
+                           : hipMemcpyAsync(s->dev_base + r->img_off, s->host_base + r->hin_off,
+                                            (size_t)r->pitch * r->h, hipMemcpyHostToDevice, s->copy);
     if (e == hipSuccess) e = hipEventRecord(s->ev_copied[r->slot], s->copy);
     ok[k] = e == hipSuccess;
   }
@@ -294,12 +281,30 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     }
     if (r->next_block == r->blocks) finishing.push_back(r);
   }
+  // the finishing requests' image entries for their ordering kernels
+  // (blocks numbered from 0 within the request's slot range) follow the
+  // block descriptors in the same upload
+  fe::ImgDev* him = reinterpret_cast<fe::ImgDev*>(hd + n);
+  for (size_t j = 0; j < finishing.size(); ++j) {
+    const Request* r = finishing[j];
+    fe::ImgDev& im = him[j];
+    im = fe::ImgDev{};
+    im.data = s->dev_base + r->img_off;
+    im.width = r->w;
+    im.height = r->h;
+    im.stride = r->pitch;
+    im.tiles_x = r->tiles_x;
+    im.tiles_y = r->tiles_y;
+    im.groups_x = r->groups_x;
+    im.groups_y = (uint32_t)(r->blocks / r->groups_x);
+  }
+  const size_t upload = (size_t)n * sizeof(fe::BlockDesc) + finishing.size() * sizeof(fe::ImgDev);
+  const fe::ImgDev* dim = reinterpret_cast<const fe::ImgDev*>(s->d_desc[slot] + n);
   lk.unlock();
   hipError_t e = hipSuccess;
   for (Request* r : first_time)
-    if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copied[r->slot], 0);   // image, cleared masks
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(s->d_desc[slot], hd, (size_t)n * sizeof(fe::BlockDesc), hipMemcpyHostToDevice, s->compute);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copied[r->slot], 0);   // the image
+  if (e == hipSuccess) e = hipMemcpyAsync(s->d_desc[slot], hd, upload, hipMemcpyHostToDevice, s->compute);
   if (e == hipSuccess) {
     fe::EncodeArgs a{};
     a.blocks = s->d_desc[slot];
@@ -311,11 +316,12 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     a.masks = s->masks;
     e = fe::launch_mns_tiles((int)s->params.b_max, s->L, s->shape, a, s->compute);
   }
-  for (Request* r : finishing) {
+  for (size_t j = 0; j < finishing.size(); ++j) {
+    Request* r = finishing[j];
     if (e != hipSuccess) break;
     // records and offsets go straight to the pinned host output
     uint8_t* hout = s->host_base + r->hout_off;
-    e = fe::launch_scatter(s->d_imgs + r->slot, 1, nullptr, r->tiles, s->cells, s->shape, s->masks + r->tile_base,
+    e = fe::launch_scatter(dim + j, 1, nullptr, r->tiles, s->cells, s->shape, s->masks + r->tile_base,
                            reinterpret_cast<uint32_t*>(s->dev_base + r->csum_off),
                            reinterpret_cast<uint64_t*>(s->dev_base + r->cbase_off),
                            s->staging + r->tile_base * (size_t)s->cells, reinterpret_cast<uint4*>(hout), r->cap,
@@ -430,14 +436,14 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
             hipMalloc(reinterpret_cast<void**>(&s->dev_base), byte_budget) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * s->cells * 16) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
-            hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&s->d_imgs), (size_t)max_slots * sizeof(fe::ImgDev)) == hipSuccess &&
-            hipHostMalloc(reinterpret_cast<void**>(&s->h_imgs), (size_t)max_slots * sizeof(fe::ImgDev),
-                          hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
-    ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc),
+    // per step: the block descriptors, then one image entry per finishing request
+    ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]),
+                       (size_t)step_blocks * (sizeof(fe::BlockDesc) + sizeof(fe::ImgDev)),
                        hipHostMallocDefault) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]), (size_t)step_blocks * sizeof(fe::BlockDesc)) ==
+         hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]),
+                   (size_t)step_blocks * (sizeof(fe::BlockDesc) + sizeof(fe::ImgDev))) ==
              hipSuccess &&
          hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
   s->ev_copied.assign(max_slots, nullptr);
@@ -483,8 +489,6 @@ void fe_server_destroy(fe_server* s) {
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : s->ev_done)
     if (ev) (void)hipEventDestroy(ev);
-  if (s->d_imgs) (void)hipFree(s->d_imgs);
-  if (s->h_imgs) (void)hipHostFree(s->h_imgs);
   if (s->dev_base) (void)hipFree(s->dev_base);
   if (s->staging) (void)hipFree(s->staging);
   if (s->masks) (void)hipFree(s->masks);
@@ -494,12 +498,12 @@ void fe_server_destroy(fe_server* s) {
   delete s;
 }
 
-fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
-                           uint64_t* req) {
-  fe::clear_error();
-  if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
-  fe_status st = fe::check_shape(w, h, stride, s->params.b_max);
-  if (st != FE_OK) return st;
+namespace {
+
+// A new request for a W x H image (not yet queued), or NULL with the error set.
+Request* new_request(fe_server* s, uint32_t w, uint32_t h, uint32_t stride, fe_status& st) {
+  st = fe::check_shape(w, h, stride, s->params.b_max);
+  if (st != FE_OK) return nullptr;
   Request* r = new Request();
   r->w = w;
   r->h = h;
@@ -511,11 +515,35 @@ fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint3
   r->blocks = (uint64_t)r->groups_x * ((r->tiles_y + s->shape.gy - 1) / s->shape.gy);
   r->cap = fe_max_transforms(w, h, s->params.b_min);
   r->chunks = (size_t)((r->tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
-  std::unique_lock<std::mutex> lk(s->mu);
   if (byte_footprint(r) > s->dev_arena.size() || slot_tiles(s, r) > s->tile_arena.size()) {
     delete r;
-    return fe::fail(FE_ERR_OOM, "request is larger than the server's device budget");
+    st = fe::fail(FE_ERR_OOM, "request is larger than the server's device budget");
+    return nullptr;
   }
+  return r;
+}
+
+// Queue a prepared request (lock not held on entry).
+void enqueue(fe_server* s, Request* r, uint64_t* req) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  r->id = s->next_id++;
+  s->queued.push_back(r);
+  s->all[r->id] = r;
+  *req = r->id;
+  lk.unlock();
+  s->cv.notify_all();
+}
+
+}  // namespace
+
+fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
+                           uint64_t* req) {
+  fe::clear_error();
+  if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  fe_status st;
+  Request* r = new_request(s, w, h, stride, st);
+  if (!r) return st;
+  std::unique_lock<std::mutex> lk(s->mu);
   const size_t hin = s->host_arena.alloc((size_t)r->pitch * h);
   if (hin == SIZE_MAX) {
     delete r;
@@ -532,13 +560,26 @@ fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint3
   } else {
     for (uint32_t y = 0; y < h; ++y) memcpy(dst + (size_t)y * r->pitch, h_img + (size_t)y * stride, w);
   }
-  lk.lock();
-  r->id = s->next_id++;
-  s->queued.push_back(r);
-  s->all[r->id] = r;
-  *req = r->id;
-  lk.unlock();
-  s->cv.notify_all();
+  enqueue(s, r, req);
+  return FE_OK;
+}
+
+fe_status fe_server_submit_pinned(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
+                                  uint64_t* req) {
+  fe::clear_error();
+  if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, h_img) != hipSuccess || attr.type != hipMemoryTypeHost) {
+    (void)hipGetLastError();
+    return fe::fail(FE_ERR_INVALID, "image is not in pinned host memory");
+  }
+  fe_status st;
+  Request* r = new_request(s, w, h, stride, st);
+  if (!r) return st;
+  r->hsrc = h_img;
+  r->hstride = stride;
+  r->t_submit = Clock::now();
+  enqueue(s, r, req);
   return FE_OK;
 }
 

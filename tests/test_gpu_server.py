@@ -152,3 +152,18 @@ def test_server_wait_reports_each_once(torch_dev, ctx):
         for k, r in enumerate(reqs):
             done, recs, _ = srv.poll(r)
             assert done and recs.tobytes() == alone(torch_dev, ctx, imgs[k]).tobytes()
+
+
+def test_server_pinned_submit(torch_dev, ctx):
+    """Zero-copy submission from pinned host memory gives the same streams;
+    pageable memory is refused."""
+    imgs = mixed_images(10, 6, 64, 512)
+    pinned = [torch_dev.from_numpy(im).pin_memory() for im in imgs]
+    with fb.Server(16, 4, THR, max_slots=8, step_blocks=64) as srv:
+        reqs = [srv.submit_pinned(p) for p in pinned]
+        res = drain(srv, reqs)
+        with pytest.raises(fb.FeError) as ei:
+            srv.submit_pinned(torch_dev.from_numpy(imgs[0].copy()))
+        assert ei.value.status == fb.FE_ERR_INVALID
+    for k, im in enumerate(imgs):
+        assert res[k][0].tobytes() == alone(torch_dev, ctx, im).tobytes()
