@@ -133,15 +133,25 @@ def bench_single(fb, ctx, img, b_max, b_min, thr, reps=10):
 
 
 def bench_decode(fb, ctx, recs, w, h, b_max, iters=12, reps=3):
+    """Both decoders on one stream: the tile decoder (the default for
+    encoder-order streams) and the per-record decoder, per iteration."""
     import torch
     out = torch.empty((h, w), dtype=torch.uint8, device="cuda")
     fn = lambda: fb.fe_decode(ctx.handle, recs, w, h, b_max, iters, out=out)
-    kms, per_call, wall = timed_kernel(fb, ctx, fb.FE_TIMING_DECODE, fn, reps)
-    # per iteration: each pixel's 2x2 domain means read (4 bytes, served from
-    # cache after the first touch: count the iterate once), one byte written,
-    # 16 bytes per transform
+    # per iteration: the iterate read once (its 2 x 2 means come from LDS or
+    # cache), one byte written per pixel, 16 bytes per transform
     alg = 2 * w * h + 16 * int(recs.shape[0])
-    return {"iterations": iters, "iter_ms": kms, "call_ms": wall, "iter_GBps": alg / (kms / 1e3) / 1e9}, out
+    res = {"iterations": iters}
+    try:
+        for mode, key in ((fb.FE_DECODE_AUTO, "tiles"), (fb.FE_DECODE_RECORDS, "records")):
+            fb.fe_decode_set_mode(ctx.handle, mode)
+            kms, per_call, wall = timed_kernel(fb, ctx, fb.FE_TIMING_DECODE, fn, reps)
+            used = "tiles" if fb.fe_decode_last(ctx.handle) == fb.FE_DECODE_TILES else "records"
+            res[key] = {"decoder": used, "iter_ms": kms, "call_ms": wall, "iter_GBps": alg / (kms / 1e3) / 1e9}
+    finally:
+        fb.fe_decode_set_mode(ctx.handle, fb.FE_DECODE_AUTO)
+    res.update(iter_ms=res["tiles"]["iter_ms"], iter_GBps=res["tiles"]["iter_GBps"])
+    return res, out
 
 
 def bench_fullsearch(fb, ctx, img, b_max, b_min, thr, reps=2):

@@ -276,6 +276,22 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
                     uint8_t* d_out, void* stream);
 
 /*
+ * Two decoders compute the same iterate bit for bit.  The tile decoder
+ * reduces the iterate to its 2 x 2 means once per 128 x 128-pixel block in
+ * LDS and writes four pixels per lane; it runs when W and H are multiples
+ * of b_max (each at least 2 b_max), d_out is 4-byte aligned, and the stream
+ * lists the tiles in raster order with each tile's transforms partitioning
+ * it in Morton order (the order fe_encode writes) with co-centred domains
+ * (Sec. 3.1).  The record decoder (one wave per transform) runs any valid
+ * stream.  fe_decode_set_mode selects FE_DECODE_AUTO (the default: tiles
+ * when allowed) or FE_DECODE_RECORDS for a context; fe_decode_last returns
+ * FE_DECODE_TILES or FE_DECODE_RECORDS for the last fe_decode on ctx.
+ */
+enum { FE_DECODE_AUTO = 0, FE_DECODE_RECORDS = 1, FE_DECODE_TILES = 2 };
+fe_status fe_decode_set_mode(fe_ctx* ctx, int mode);
+int fe_decode_last(const fe_ctx* ctx);
+
+/*
  * Exhaustive search of explicit ranges (Sec. 1): for each range of side
  * `block` (4, 8 or 16) at d_xy[i] (x | y << 16, multiples of block), find
  * the best of all (W - 2B + 1)(H - 2B + 1) step-1 domains, 8 isometries and

@@ -75,6 +75,8 @@ _SIGNATURES = {
     "fe_plan_launch": (ctypes.c_int, [_VP, _VP]),
     "fe_plan_destroy": (None, [_VP]),
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
+    "fe_decode_set_mode": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "fe_decode_last": (ctypes.c_int, [_VP]),
     "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
                                         ctypes.POINTER(_VP)]),
@@ -290,6 +292,17 @@ def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: 
     return out
 
 
+FE_DECODE_AUTO, FE_DECODE_RECORDS, FE_DECODE_TILES = 0, 1, 2
+
+
+def fe_decode_set_mode(ctx: int, mode: int) -> None:
+    _check(load().fe_decode_set_mode(ctx, mode))
+
+
+def fe_decode_last(ctx: int) -> int:
+    return int(load().fe_decode_last(ctx))
+
+
 def fe_full_search_ranges(ctx: int, img, block: int, xy, out=None, stream=None):
     """Exhaustive best match of explicit ranges; returns an (n, 4) int32
     tensor: domain index, e | k << 8 | m << 16, S low, S high."""
@@ -499,3 +512,9 @@ class Context:
 
     def decode(self, transforms, width, height, b_max, iters, start=None, **kw):
         return fe_decode(self.handle, transforms, width, height, b_max, iters, start=start, **kw)
+
+    def decode_mode(self, mode):
+        fe_decode_set_mode(self.handle, mode)
+
+    def decode_last(self):
+        return fe_decode_last(self.handle)

@@ -165,6 +165,301 @@ __global__ __launch_bounds__(256) void iter_kernel(DecodeArgs a, const uint8_t* 
   }
 }
 
+// ---------------------------------------------------------------- tiles
+// Tile-ordered decoding.  Streams whose records partition every top tile in
+// order (consecutive Morton intervals of 4 x 4-pixel cells, y bit above x,
+// tiles in raster order) and use the co-centred domains are decoded one
+// block of 128 x 128 pixels per workgroup: the block's domain region of
+// the iterate is reduced to H0 in LDS once, every record's domain sum comes
+// from there, and the output is written four pixels at a time.  Any other
+// stream uses iter_kernel.
+
+__device__ __forceinline__ int cell_morton(int cx, int cy) {
+  int code = 0;
+#pragma unroll
+  for (int bit = 0; bit < 3; ++bit) code |= (((cx >> bit) & 1) << (2 * bit)) | (((cy >> bit) & 1) << (2 * bit + 1));
+  return code;
+}
+
+__device__ __forceinline__ int cocentred(int p, int B, int extent) { return clampi(p - B / 2, 0, extent - 2 * B); }
+
+// One lane per record: the first record of each tile, and whether the
+// stream meets the conditions above (flag set when it does not).
+__global__ __launch_bounds__(256) void tile_setup_kernel(DecodeArgs a, uint32_t* tile_start, uint32_t* flag) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int W = (int)a.width, H = (int)a.height, bm = (int)a.b_max;
+  const int tiles_x = W / bm, ntiles = tiles_x * (H / bm), cells = (bm / 4) * (bm / 4);
+  auto info = [&](uint64_t k, int& tile, int& key, int& end, bool& centred) {
+    const Fields f = unpack(a.recs[k]);
+    const int B = bm >> f.level;
+    tile = (f.y / bm) * tiles_x + f.x / bm;
+    key = cell_morton((f.x % bm) >> 2, (f.y % bm) >> 2);
+    end = key + (B >> 2) * (B >> 2);
+    centred = f.dx == cocentred(f.x, B, W) && f.dy == cocentred(f.y, B, H);
+  };
+  int tile, key, end;
+  bool centred;
+  info(i, tile, key, end, centred);
+  bool ok = centred;
+  bool first = true;
+  if (i == 0) {
+    ok = ok && tile == 0 && key == 0;
+  } else {
+    int tp, kp, ep;
+    bool cp;
+    info(i - 1, tp, kp, ep, cp);
+    if (tile == tp) {
+      ok = ok && key == ep;
+      first = false;
+    } else {
+      ok = ok && tile == tp + 1 && key == 0 && ep == cells;
+    }
+  }
+  if (i == a.n - 1) ok = ok && end == cells && tile == ntiles - 1;
+  if (!ok) atomicOr(flag, 1u);
+  if (first && tile >= 0 && tile < ntiles) tile_start[tile] = (uint32_t)i;
+  if (i == a.n - 1) tile_start[ntiles] = (uint32_t)a.n;
+}
+
+// A decode plan splits the image into blocks of 64 x 64 pixels (partial at
+// the right and bottom edges).  Each block's transforms become pieces: a
+// phase-1 transform is one piece, a phase-2 transform four (one per
+// sub-block, with its own domain, contrast and luminance, Sec. 3.3).  Every
+// piece is an aligned square of side b >= 4 inside the block, so a block
+// holds at most 256 pieces, and each 4 x 4-pixel cell of the block lies in
+// exactly one.  Per block the plan stores the piece index of each cell
+// (256 bytes) and up to 256 pieces of 8 bytes:
+//   word 0: wx | wy << 6 | e << 12 | c << 15 | phase2 << 20 | log2(b / 4) << 21
+//   word 1: L = 8 n m + 4 n (phase 1) or 20 n O_c + 10 n (phase 2), n = b^2,
+// with (wx, wy) the domain origin in the block's H0 region (below) and c the
+// contrast numerator (k of k/8, or the set's value of c/20).  Everything in
+// the plan is fixed by the stream; only Sum d changes between iterations.
+constexpr int kDecTile = 64;                 // block side (pixels)
+constexpr int kDecCells = (kDecTile / 4) * (kDecTile / 4);
+
+struct DecRegion {
+  int X0, Y0, bw, bh;   // block origin and size (pixels)
+  int ax0, ay0;         // origin of the staged region (multiple of 8)
+  int n8x, n8y;         // 8 x 8-pixel groups staged per side
+};
+
+// The staged region is the union of the co-centred domains of the block's
+// top tiles (every piece's domain lies inside it), origin rounded down to 8.
+__device__ __forceinline__ DecRegion dec_region(int blk, int W, int H, int bm) {
+  DecRegion r;
+  const int nbx = (W + kDecTile - 1) / kDecTile;
+  r.X0 = (blk % nbx) * kDecTile;
+  r.Y0 = (blk / nbx) * kDecTile;
+  r.bw = min(kDecTile, W - r.X0);
+  r.bh = min(kDecTile, H - r.Y0);
+  const int rx0 = clampi(r.X0 - bm / 2, 0, W - 2 * bm);
+  const int rx1 = clampi(r.X0 + r.bw - bm - bm / 2, 0, W - 2 * bm) + 2 * bm;
+  const int ry0 = clampi(r.Y0 - bm / 2, 0, H - 2 * bm);
+  const int ry1 = clampi(r.Y0 + r.bh - bm - bm / 2, 0, H - 2 * bm) + 2 * bm;
+  r.ax0 = rx0 & ~7;
+  r.ay0 = ry0 & ~7;
+  r.n8x = (rx1 - r.ax0 + 7) >> 3;
+  r.n8y = (ry1 - r.ay0 + 7) >> 3;
+  return r;
+}
+
+// One workgroup per block: gather the block's transforms (one run of
+// consecutive records per tile row), expand them into pieces and the cell
+// map.  Runs once per decode call.
+__global__ __launch_bounds__(256) void dec_plan_kernel(DecodeArgs a, const uint32_t* __restrict__ tile_start,
+                                                       uint8_t* __restrict__ cells, uint2* __restrict__ pieces) {
+  __shared__ uint32_t s_run0[kDecTile / 4], s_runs[kDecTile / 4 + 1], s_count;
+  __shared__ uint8_t s_cell[kDecCells];
+  const int tid = threadIdx.x, blk = blockIdx.x;
+  const int W = (int)a.width, H = (int)a.height, bm = (int)a.b_max;
+  const DecRegion g = dec_region(blk, W, H, bm);
+  const int tiles_x = W / bm, gxn = g.bw / bm, gyn = g.bh / bm;
+  const int t0x = g.X0 / bm, t0y = g.Y0 / bm;
+  if (tid < gyn) {
+    const int t0 = (t0y + tid) * tiles_x + t0x;
+    s_run0[tid] = tile_start[t0];
+    s_runs[tid + 1] = tile_start[t0 + gxn] - tile_start[t0];
+  }
+  if (tid == 0) s_count = 0;
+  __syncthreads();
+  if (tid == 0) {
+    s_runs[0] = 0;
+    for (int k = 0; k < gyn; ++k) s_runs[k + 1] += s_runs[k];
+  }
+  __syncthreads();
+  const int nrec = (int)s_runs[gyn];
+  uint2* out = pieces + (size_t)blk * kDecCells;
+  for (int j = tid; j < nrec; j += 256) {
+    int row = 0;
+    while (row + 1 < gyn && (int)s_runs[row + 1] <= j) ++row;
+    const Fields f = unpack(a.recs[s_run0[row] + (uint32_t)(j - (int)s_runs[row])]);
+    const int B = bm >> f.level;
+    const int np = f.flags ? 4 : 1, b = f.flags ? B / 2 : B;
+    const uint32_t p0 = atomicAdd(&s_count, (uint32_t)np);
+    int c1 = 0, c2 = 0, delta = 0;
+    if (f.flags) phase2_consts(f.level + 1, c1, c2, delta);
+    const int lb = log2i(b) - 2, n = b * b;
+    for (int c = 0; c < np; ++c) {
+      const int px = f.x + (f.flags ? (c & 1) * b : 0), py = f.y + (f.flags ? (c >> 1) * b : 0);
+      uint32_t w0, w1;
+      if (f.flags == 0) {
+        const int wx = (f.dx - g.ax0) >> 1, wy = (f.dy - g.ay0) >> 1;
+        w0 = (uint32_t)wx | (uint32_t)wy << 6 | (uint32_t)f.iso << 12 | (uint32_t)f.s_idx << 15 | (uint32_t)lb << 21;
+        w1 = (uint32_t)(8 * n * f.lum + 4 * n);
+      } else {
+        const int wx = (cocentred(px, b, W) - g.ax0) >> 1, wy = (cocentred(py, b, H) - g.ay0) >> 1;
+        const int O0 = f.lum + f.d0, O1 = f.lum + f.d1, O2 = f.lum + f.d2;
+        const int O = c == 0 ? O0 : (c == 1 ? O1 : (c == 2 ? O2 : 4 * f.lum - O0 - O1 - O2));
+        const int cv = ((f.s_idx >> c) & 1) ? c2 : c1;
+        w0 = (uint32_t)wx | (uint32_t)wy << 6 | (uint32_t)cv << 15 | 1u << 20 | (uint32_t)lb << 21;
+        w1 = (uint32_t)(20 * n * O + 10 * n);
+      }
+      const uint32_t p = p0 + (uint32_t)c;
+      out[p] = make_uint2(w0, w1);
+      const int cx0 = (px - g.X0) >> 2, cy0 = (py - g.Y0) >> 2, cs = b >> 2;
+      for (int k = 0; k < cs * cs; ++k) s_cell[(cy0 + k / cs) * (kDecTile / 4) + cx0 + k % cs] = (uint8_t)p;
+    }
+  }
+  __syncthreads();
+  cells[(size_t)blk * kDecCells + tid] = s_cell[tid];
+}
+
+template <int BMAX>
+struct DecGeo {
+  static constexpr int NG8 = (kDecTile + BMAX + 6 + 7) / 8;   // max 8-pixel groups per region side
+  static constexpr int HS = 4 * NG8;                          // H0 entries per region side
+  static constexpr int HP = HS + 4;                           // H0 row pitch (bytes)
+};
+
+// Four H0 bytes starting at column `col` of row `row` (any alignment).
+__device__ __forceinline__ uint32_t h0_quad(const uint32_t* t, int pitch_words, int row, int col) {
+  const int w = row * pitch_words + (col >> 2);
+  return __builtin_amdgcn_alignbyte(t[w + 1], t[w], (uint32_t)(col & 3));
+}
+
+// One Jacobi iteration over one block: stage the region's H0 and its
+// transpose, every lane adds its cell's quarter-by-quarter share of its
+// piece's domain sum (the piece's b x b domain block split into 4 x 4
+// sub-blocks, one per cell of the piece), then writes its cell's 16 pixels.
+template <int BMAX>
+__global__ __launch_bounds__(256) void dec_iter_kernel(DecodeArgs a, uint32_t n_blk,
+                                                       const uint8_t* __restrict__ cells,
+                                                       const uint2* __restrict__ pieces,
+                                                       const uint8_t* __restrict__ cur, uint8_t* __restrict__ nxt) {
+  using D = DecGeo<BMAX>;
+  constexpr int PW = D::HP / 4;
+  __shared__ uint32_t s_h0[D::HS * PW + 1], s_h0t[D::HS * PW + 1];
+  __shared__ uint32_t s_sd[kDecCells];
+  const int tid = threadIdx.x;
+  // XCD-aware order: consecutive blocks (one band of block rows) share an XCD
+  const uint32_t per = (n_blk + 7u) >> 3;
+  const uint32_t blk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (blk >= n_blk) return;
+  const int W = (int)a.width, H = (int)a.height;
+  const DecRegion g = dec_region((int)blk, W, H, BMAX);
+  // this lane's cell and piece (the plan does not change between iterations)
+  const int cx = tid & (kDecTile / 4 - 1), cy = tid / (kDecTile / 4);
+  const bool live = 4 * cx < g.bw && 4 * cy < g.bh;
+  uint32_t p = 0u;
+  uint2 pc = make_uint2(0u, 0u);
+  if (live) {
+    p = cells[(size_t)blk * kDecCells + tid];
+    pc = pieces[(size_t)blk * kDecCells + p];
+  }
+  // ---- stage: one 8 x 8-pixel group per lane -> 4 x 4 H0 and H0^T
+  {
+    const int gx = tid % D::NG8, gy = tid / D::NG8;
+    if (gy < g.n8y && gx < g.n8x) {
+      const int x = g.ax0 + 8 * gx;
+      uint32_t v[8][2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        v[r][0] = v[r][1] = 0u;
+        const int y = g.ay0 + 8 * gy + r;
+        if (y < H) {
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(cur + (size_t)y * W + x);
+          if (x + 8 <= W) {
+            v[r][0] = src[0];
+            v[r][1] = src[1];
+          } else if (x < W) {
+            v[r][0] = src[0];
+          }
+        }
+      }
+      uint32_t hr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hr[q] = mean2x2_x4(v[2 * q][0], v[2 * q][1], v[2 * q + 1][0], v[2 * q + 1][1]);
+        s_h0[(4 * gy + q) * PW + gx] = hr[q];
+      }
+      const uint32_t u0 = __builtin_amdgcn_perm(hr[1], hr[0], 0x05010400u);
+      const uint32_t u1 = __builtin_amdgcn_perm(hr[1], hr[0], 0x07030602u);
+      const uint32_t w0 = __builtin_amdgcn_perm(hr[3], hr[2], 0x05010400u);
+      const uint32_t w1 = __builtin_amdgcn_perm(hr[3], hr[2], 0x07030602u);
+      s_h0t[(4 * gx + 0) * PW + gy] = __builtin_amdgcn_perm(w0, u0, 0x05040100u);
+      s_h0t[(4 * gx + 1) * PW + gy] = __builtin_amdgcn_perm(w0, u0, 0x07060302u);
+      s_h0t[(4 * gx + 2) * PW + gy] = __builtin_amdgcn_perm(w1, u1, 0x05040100u);
+      s_h0t[(4 * gx + 3) * PW + gy] = __builtin_amdgcn_perm(w1, u1, 0x07060302u);
+    }
+  }
+  s_sd[tid] = 0u;
+  __syncthreads();
+  // ---- the piece's fields and this cell's place in it
+  const int wx = (int)(pc.x & 63u), wy = (int)((pc.x >> 6) & 63u);
+  const int e = (int)((pc.x >> 12) & 7u), cnum = (int)((pc.x >> 15) & 31u);
+  const bool ph2 = (pc.x >> 20) & 1u;
+  const int lb = (int)((pc.x >> 21) & 3u) + 2, b = 1 << lb;
+  const int rx = (4 * cx) & (b - 1), ry = (4 * cy) & (b - 1);
+  if (live) {
+    uint32_t acc = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_udot4(h0_quad(s_h0, PW, wy + ry + r, wx + rx), 0x01010101u, acc, false);
+    atomicAdd(&s_sd[p], acc);
+  }
+  __syncthreads();
+  if (!live) return;
+  // ---- output: clamp((c (n d - Sum d) + L) >> shift) per pixel, divided by
+  // 20 for a phase-2 piece
+  const int shift = ph2 ? 2 * lb : 3 + 2 * lb;
+  const int K = cnum << (2 * lb);
+  const int C = (int)pc.y - cnum * (int)s_sd[p];
+  // source rows / columns: for e < 4 row i of the range reads H0 row si with
+  // columns running forward or backward; for e >= 4 it reads H0^T row sj
+  const bool tr = e >= 4;
+  const bool flip_row = tr ? (e & 1) : (e & 2);     // on the index that follows the range column
+  const bool flip_col = tr ? (e & 2) : (e & 1);
+  const uint32_t* tab = tr ? s_h0t : s_h0;
+  const int base_row = tr ? wx : wy, base_col = tr ? wy : wx;
+  uint8_t* dst = nxt + (size_t)(g.Y0 + 4 * cy) * W + g.X0 + 4 * cx;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ry + r;
+    uint32_t q;
+    if (ph2) {
+      q = h0_quad(s_h0, PW, wy + i, wx + rx);
+    } else {
+      // e < 4: row si = i or b-1-i, columns rx.. (or mirrored, reversed);
+      // e >= 4: H0^T row sj = i or b-1-i, columns likewise
+      const int srow = (tr ? flip_col : flip_row) ? b - 1 - i : i;
+      const bool rev = tr ? flip_row : flip_col;
+      const int scol = rev ? b - 4 - rx : rx;
+      q = h0_quad(tab, PW, base_row + srow, base_col + scol);
+      if (rev) q = __builtin_amdgcn_perm(0u, q, 0x00010203u);
+    }
+    uint32_t word = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = (int)((q >> (8 * k)) & 0xffu);
+      const int num = K * d + C;
+      uint32_t v = num < 0 ? 0u : (uint32_t)num >> shift;
+      if (ph2) v /= 20u;
+      word |= min(v, 255u) << (8 * k);
+    }
+    *reinterpret_cast<uint32_t*>(dst + (size_t)r * W) = word;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t s) {
@@ -177,6 +472,37 @@ hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint
   const uint64_t n = (uint64_t)w * h;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_tile_setup(const DecodeArgs& a, uint32_t* tile_start, uint32_t* flag, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_setup_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, tile_start, flag);
+  return hipGetLastError();
+}
+
+size_t decode_plan_blocks(uint32_t w, uint32_t h) {
+  return (size_t)((w + kDecTile - 1) / kDecTile) * ((h + kDecTile - 1) / kDecTile);
+}
+
+hipError_t launch_decode_plan(const DecodeArgs& a, const uint32_t* tile_start, uint8_t* cells, uint2* pieces,
+                              hipStream_t s) {
+  const unsigned grid = (unsigned)decode_plan_blocks(a.width, a.height);
+  hipLaunchKernelGGL(dec_plan_kernel, dim3(grid), dim3(256), 0, s, a, tile_start, cells, pieces);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_tile_iter(const DecodeArgs& a, const uint8_t* cells, const uint2* pieces,
+                                   const uint8_t* cur, uint8_t* nxt, hipStream_t s) {
+  const uint32_t n_blk = (uint32_t)decode_plan_blocks(a.width, a.height);
+  const unsigned grid = 8u * ((n_blk + 7u) >> 3);
+  switch (a.b_max) {
+    case 32: hipLaunchKernelGGL(dec_iter_kernel<32>, dim3(grid), dim3(256), 0, s, a, n_blk, cells, pieces, cur, nxt); break;
+    case 16: hipLaunchKernelGGL(dec_iter_kernel<16>, dim3(grid), dim3(256), 0, s, a, n_blk, cells, pieces, cur, nxt); break;
+    case 8: hipLaunchKernelGGL(dec_iter_kernel<8>, dim3(grid), dim3(256), 0, s, a, n_blk, cells, pieces, cur, nxt); break;
+    case 4: hipLaunchKernelGGL(dec_iter_kernel<4>, dim3(grid), dim3(256), 0, s, a, n_blk, cells, pieces, cur, nxt); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

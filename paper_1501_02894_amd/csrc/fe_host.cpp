@@ -58,6 +58,14 @@ struct fe_ctx {
   uint32_t* flags = nullptr;          // small device counters
   uint8_t* tmp_img = nullptr;
   size_t tmp_n = 0;
+  uint32_t* dec_tiles = nullptr;      // decoder: first record of each top tile
+  size_t dec_tiles_n = 0;
+  uint8_t* dec_cells = nullptr;       // decoder plan: cell -> piece per block
+  size_t dec_cells_n = 0;
+  uint2* dec_pieces = nullptr;        // decoder plan: pieces per block
+  size_t dec_pieces_n = 0;
+  bool last_decode_tiled = false;     // which decoder the last fe_decode ran
+  int decode_mode = FE_DECODE_AUTO;
   fe::TileShape shape_override[33][5] = {};
   // kernel timing (fe_timing_enable)
   bool timing = false;
@@ -492,6 +500,9 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->offsets);
   (void)hipFree(c->flags);
   (void)hipFree(c->tmp_img);
+  (void)hipFree(c->dec_tiles);
+  (void)hipFree(c->dec_cells);
+  (void)hipFree(c->dec_pieces);
   if (c->ev) {
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
       if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -561,24 +572,57 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   fe::DecodeArgs a{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
-  FE_HIP(fe::launch_zero_u32(ctx->flags, 1, s), "zero flag");
+  // Tile-ordered decoding needs whole top tiles, room for a domain of the
+  // top size, word-aligned rows and a stream that partitions every tile in
+  // stream order with co-centred domains (checked on the device below).
+  const bool tiled_shape = ctx->decode_mode == FE_DECODE_AUTO && n > 0 && w % b_max == 0 && h % b_max == 0 && w >= 2 * b_max && h >= 2 * b_max &&
+                           ((uintptr_t)d_out & 3) == 0;
+  const size_t ntiles = (size_t)(w / b_max) * (h / b_max);
+  const size_t nblk = fe::decode_plan_blocks(w, h);
+  if (tiled_shape) {
+    fe_status st = ensure(ctx->dec_tiles, ctx->dec_tiles_n, ntiles + 1, "tile starts");
+    if (st == FE_OK) st = ensure(ctx->dec_cells, ctx->dec_cells_n, nblk * 256, "decode plan cells");
+    if (st == FE_OK) st = ensure(ctx->dec_pieces, ctx->dec_pieces_n, nblk * 256, "decode plan pieces");
+    if (st != FE_OK) return st;
+  }
+  FE_HIP(fe::launch_zero_u32(ctx->flags, 2, s), "zero flags");
   FE_HIP(fe::launch_decode_check(a, ctx->flags, s), "check launch");
-  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "flag read-back");
+  if (tiled_shape) FE_HIP(fe::launch_decode_tile_setup(a, ctx->dec_tiles, ctx->flags + 1, s), "tile setup");
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+         "flag read-back");
   FE_HIP(hipStreamSynchronize(s), "transform check");
   const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
   if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms are out of range for a %ux%u image", bad, w, h);
+  const bool tiled = tiled_shape && (uint32_t)(ctx->h_scalars[0] >> 32) == 0u;
   fe_status st = ensure(ctx->tmp_img, ctx->tmp_n, (size_t)w * h, "decode buffer");
   if (st != FE_OK) return st;
   uint8_t* buf[2] = {d_out, ctx->tmp_img};
   const int s0 = (int)(iters & 1u);   // iterate t lives in buf[s0 ^ (t & 1)]; t = iters in d_out
   FE_HIP(fe::launch_decode_fill(buf[1 - s0], d_start, w, h, s), "fill");
   FE_HIP(fe::launch_decode_fill(buf[s0], d_start, w, h, s), "fill");
+  ctx->last_decode_tiled = tiled;
+  if (tiled && iters) FE_HIP(fe::launch_decode_plan(a, ctx->dec_tiles, ctx->dec_cells, ctx->dec_pieces, s), "plan");
   for (uint32_t t = 0; t < iters; ++t) {
     Timed tm(ctx, FE_TIMING_DECODE, s);
-    FE_HIP(fe::launch_decode_iter(a, buf[s0 ^ (int)(t & 1u)], buf[s0 ^ (int)((t + 1) & 1u)], s), "decode launch");
+    const uint8_t* cur = buf[s0 ^ (int)(t & 1u)];
+    uint8_t* nxt = buf[s0 ^ (int)((t + 1) & 1u)];
+    if (tiled)
+      FE_HIP(fe::launch_decode_tile_iter(a, ctx->dec_cells, ctx->dec_pieces, cur, nxt, s), "decode launch");
+    else
+      FE_HIP(fe::launch_decode_iter(a, cur, nxt, s), "decode launch");
   }
   return FE_OK;
 }
+
+fe_status fe_decode_set_mode(fe_ctx* ctx, int mode) {
+  fe::clear_error();
+  if (!ctx) return fe::fail(FE_ERR_INVALID, "NULL context");
+  if (mode != FE_DECODE_AUTO && mode != FE_DECODE_RECORDS) return fe::fail(FE_ERR_INVALID, "bad decode mode %d", mode);
+  ctx->decode_mode = mode;
+  return FE_OK;
+}
+
+int fe_decode_last(const fe_ctx* ctx) { return ctx && ctx->last_decode_tiled ? FE_DECODE_TILES : FE_DECODE_RECORDS; }
 
 int fe_tile_shapes(uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy, int max_out) {
   if (!fe::is_pow2(b_max) || !fe::is_pow2(b_min) || b_min < 4 || b_max > 32 || b_min > b_max) return 0;

@@ -101,6 +101,18 @@ hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint
                               hipStream_t stream);
 hipError_t launch_decode_iter(const DecodeArgs& a, const uint8_t* cur, uint8_t* nxt,
                               hipStream_t stream);
+// Tile-ordered decoder: tile_start[t] = first record of top tile t (n at
+// the end); *flag is set when the stream is not tile-ordered with
+// co-centred domains, and the tile kernel must not run then.
+hipError_t launch_decode_tile_setup(const DecodeArgs& a, uint32_t* tile_start, uint32_t* flag,
+                                    hipStream_t stream);
+// Decode plan (64 x 64-pixel blocks): per block 256 cell -> piece bytes and
+// 256 piece slots of 8 bytes, built once per call from tile_start.
+size_t decode_plan_blocks(uint32_t w, uint32_t h);
+hipError_t launch_decode_plan(const DecodeArgs& a, const uint32_t* tile_start, uint8_t* cells, uint2* pieces,
+                              hipStream_t stream);
+hipError_t launch_decode_tile_iter(const DecodeArgs& a, const uint8_t* cells, const uint2* pieces,
+                                   const uint8_t* cur, uint8_t* nxt, hipStream_t stream);
 
 // Exhaustive search (one image).  Plans, the 2x2 phase planes, per-level
 // domain sums, the MFMA search of a list of ranges (best key per range),

@@ -1,0 +1,142 @@
+"""GPU parity of both decoders (tile-ordered and per-record) against the
+oracle's integer decoder, through the C ABI.
+
+Decoding is exact integer arithmetic on both sides, so every pixel of every
+case is compared exactly.  Streams come from the encoder (oracle) and from
+seeded random quadtrees (tests/streams.py) that reach every record kind:
+phase-2 records at every level, 4 x 4 leaves next to whole tiles, image
+sides that leave partial 128 x 128 blocks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import decode as odec
+from oracle import fullsearch, metrics, mns
+from paper_1501_02894_amd import binding as fb
+from paper_1501_02894_amd import synth
+from streams import random_stream
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = fb.Context(0)
+    yield c
+    c.close()
+
+
+def _t(torch, rec):
+    return torch.from_numpy(np.ascontiguousarray(rec).view(np.uint8).reshape(-1, 16).copy()).cuda()
+
+
+def _decode_both(torch, ctx, rec, W, H, bm, iters, start=None, expect=fb.FE_DECODE_TILES):
+    t = _t(torch, rec)
+    s = None if start is None else torch.from_numpy(np.ascontiguousarray(start)).cuda()
+    out = {}
+    try:
+        for mode in (fb.FE_DECODE_AUTO, fb.FE_DECODE_RECORDS):
+            ctx.decode_mode(mode)
+            out[mode] = ctx.decode(t, W, H, bm, iters, start=s).cpu().numpy()
+            used = ctx.decode_last()
+            assert used == (expect if mode == fb.FE_DECODE_AUTO else fb.FE_DECODE_RECORDS), (mode, used)
+    finally:
+        ctx.decode_mode(fb.FE_DECODE_AUTO)
+    return out[fb.FE_DECODE_AUTO], out[fb.FE_DECODE_RECORDS]
+
+
+RANDOM_CASES = [
+    # W, H, b_max, b_min, seed
+    (96, 160, 32, 4, 1), (160, 96, 32, 8, 2), (64, 48, 16, 4, 3), (112, 80, 8, 4, 4),
+    (64, 64, 4, 4, 5), (264, 136, 8, 4, 6), (384, 256, 32, 4, 7), (288, 160, 16, 8, 8),
+    (8, 8, 4, 4, 9), (1040, 528, 16, 4, 10),
+]
+
+
+@pytest.mark.parametrize("W,H,bm,bmin,seed", RANDOM_CASES)
+def test_random_streams(torch_dev, ctx, W, H, bm, bmin, seed):
+    log(f"decode random {W}x{H} b{bm}/{bmin}")
+    rec = random_stream(W, H, bm, bmin, seed)
+    start = np.random.default_rng(seed).integers(0, 256, (H, W)).astype(np.uint8)
+    tiles, records = _decode_both(torch_dev, ctx, rec, W, H, bm, 3, start=start)
+    want = odec.decode(rec, W, H, bm, 3, start=start)
+    np.testing.assert_array_equal(tiles, want)
+    np.testing.assert_array_equal(records, want)
+
+
+@pytest.mark.parametrize("name,b_max,b_min,thr", [("c1", 8, 4, [600]), ("c2", 16, 4, [300, 200])])
+def test_encoded_streams(torch_dev, ctx, name, b_max, b_min, thr):
+    log(f"decode encoded {name}")
+    img = synth.workload(name)
+    H, W = img.shape
+    rec = mns.encode(img, b_max, b_min, thr)
+    for iters in (0, 1, 12):
+        tiles, records = _decode_both(torch_dev, ctx, rec, W, H, b_max, iters)
+        want = odec.decode(rec, W, H, b_max, iters)
+        np.testing.assert_array_equal(tiles, want)
+        np.testing.assert_array_equal(records, want)
+
+
+def test_out_of_order_stream_uses_records(torch_dev, ctx):
+    """A valid stream in another order decodes to the same image, on the
+    per-record decoder."""
+    rec = random_stream(64, 64, 16, 4, 11)
+    perm = np.random.default_rng(11).permutation(rec.size)
+    shuffled = rec[perm]
+    tiles, records = _decode_both(torch_dev, ctx, shuffled, 64, 64, 16, 2, expect=fb.FE_DECODE_RECORDS)
+    want = odec.decode(rec, 64, 64, 16, 2)
+    np.testing.assert_array_equal(tiles, want)
+    np.testing.assert_array_equal(records, want)
+
+
+def test_full_search_stream_uses_records(torch_dev, ctx):
+    """Exhaustive-search records carry arbitrary domain origins."""
+    img = synth.workload("c1")
+    rec = fullsearch.encode(img, 8, 4, [600])
+    expect = fb.FE_DECODE_TILES
+    centred = (rec["dx"] == mns.domain_origin(rec["x"], 8 >> rec["level"].astype(np.int64), 64)) & \
+              (rec["dy"] == mns.domain_origin(rec["y"], 8 >> rec["level"].astype(np.int64), 64))
+    if not np.all(centred):
+        expect = fb.FE_DECODE_RECORDS
+    tiles, records = _decode_both(torch_dev, ctx, rec, 64, 64, 8, 3, expect=expect)
+    want = odec.decode(rec, 64, 64, 8, 3)
+    np.testing.assert_array_equal(tiles, want)
+    np.testing.assert_array_equal(records, want)
+
+
+def test_unaligned_output_uses_records(torch_dev, ctx):
+    torch = torch_dev
+    rec = random_stream(64, 32, 16, 4, 12)
+    buf = torch.empty(64 * 32 + 4, dtype=torch.uint8, device="cuda")
+    out = buf[1:1 + 64 * 32].view(32, 64)
+    ctx.decode(_t(torch, rec), 64, 32, 16, 2, out=out)
+    assert ctx.decode_last() == fb.FE_DECODE_RECORDS
+    np.testing.assert_array_equal(out.cpu().numpy(), odec.decode(rec, 64, 32, 16, 2))
+
+
+@pytest.mark.slow
+def test_decode_c3(torch_dev, ctx):
+    """C3 (4096^2, 32 -> 4, 12 iterations): both decoders against the
+    oracle over the whole image; PSNR within 0.01 dB follows."""
+    log("decode c3 (12 iterations, both decoders)")
+    img = synth.workload("c3")
+    rec = mns.encode(img, 32, 4, [150, 100, 64])
+    tiles, records = _decode_both(torch_dev, ctx, rec, 4096, 4096, 32, 12)
+    want = odec.decode(rec, 4096, 4096, 32, 12)
+    np.testing.assert_array_equal(tiles, want)
+    np.testing.assert_array_equal(records, want)
+    assert abs(metrics.psnr(img, tiles) - metrics.psnr(img, want)) <= 0.01

@@ -328,13 +328,3 @@ def test_decode_zero_iterations_and_bad_input(torch_dev, ctx):
     assert ei.value.status == fb.FE_ERR_INVALID
 
 
-@pytest.mark.slow
-def test_decode_c3(torch_dev, ctx):
-    log("decode c3 (12 iterations)")
-    img = synth.workload("c3")
-    rec = mns.encode(img, 32, 4, [150, 100, 64])
-    t = torch_dev.from_numpy(np.ascontiguousarray(rec).view(np.uint8).reshape(-1, 16).copy()).cuda()
-    got = ctx.decode(t, 4096, 4096, 32, 12).cpu().numpy()
-    want = odec.decode(rec, 4096, 4096, 32, 12)
-    np.testing.assert_array_equal(got, want)
-    assert abs(metrics.psnr(img, got) - metrics.psnr(img, want)) <= 0.01
