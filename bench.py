@@ -252,6 +252,32 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     return res
 
 
+def copy_calibration(torch, dev):
+    """Three device copies of 256 MiB: the counter readings of a kernel
+    whose traffic is known (scales FETCH_SIZE / WRITE_SIZE)."""
+    src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(3)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 256 << 20
+
+
+def decode_only(fb, args):
+    import torch
+    from paper_1501_02894_amd import synth
+    img = synth.workload("c3")
+    ctx = fb.Context(0)
+    recs = fb.to_records(ctx.encode(torch.from_numpy(img).cuda(), 32, 4, [150, 100, 64]))
+    t = torch.from_numpy(np.ascontiguousarray(recs).view(np.uint8).reshape(-1, 16).copy()).cuda()
+    res, _ = bench_decode(fb, ctx, t, 4096, 4096, 32, iters=12, reps=args.steps)
+    out = {"workload": "c3 decode (4096^2, 32 -> 4, 12 iterations)", "records": int(recs.size), "c3_decode": res}
+    if args.copy_calibration:
+        out["copy_calibration_bytes"] = copy_calibration(torch, torch.device("cuda:0"))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +293,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--decode-only", action="store_true",
+                    help="only decode C3 (4096^2, 32 -> 4) with both decoders (a profiling workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -277,6 +305,9 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
+    if args.decode_only:
+        decode_only(fb, args)
+        return
     t_gen = time.perf_counter()
     images, _ = gen_images(args.images)
     t_gen = time.perf_counter() - t_gen
@@ -436,12 +467,7 @@ def main():
         result["serving"] = serving
 
     if args.copy_calibration:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(3)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = 256 << 20
+        result["copy_calibration_bytes"] = copy_calibration(torch, dev)
 
     if not args.no_cpu_baseline:
         os.environ.setdefault("OMP_NUM_THREADS", "1")

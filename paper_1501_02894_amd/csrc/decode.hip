@@ -80,9 +80,19 @@ __global__ __launch_bounds__(256) void check_kernel(DecodeArgs a, uint32_t* bad)
   if (bad_record(unpack(a.recs[i]), (int)a.width, (int)a.height, (int)a.b_max)) atomicAdd(bad, 1u);
 }
 
+// 16 bytes per lane: one 16-byte copy when both pointers allow it, else
+// byte by byte.
 __global__ __launch_bounds__(256) void fill_kernel(uint8_t* dst, const uint8_t* src, uint64_t n) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src ? src[i] : (uint8_t)128;
+  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16u;
+  if (i >= n) return;
+  const bool wide = i + 16u <= n && ((uintptr_t)dst & 15u) == 0 && (!src || ((uintptr_t)src & 15u) == 0);
+  if (wide) {
+    *reinterpret_cast<uint4*>(dst + i) =
+        src ? *reinterpret_cast<const uint4*>(src + i) : make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+    return;
+  }
+  const uint64_t end = i + 16u < n ? i + 16u : n;
+  for (uint64_t k = i; k < end; ++k) dst[k] = src ? src[k] : (uint8_t)128;
 }
 
 template <int WIDTH>
@@ -358,51 +368,48 @@ __global__ __launch_bounds__(256) void dec_iter_kernel(DecodeArgs a, uint32_t n_
   if (blk >= n_blk) return;
   const int W = (int)a.width, H = (int)a.height;
   const DecRegion g = dec_region((int)blk, W, H, BMAX);
-  // this lane's cell and piece (the plan does not change between iterations)
+  // Every load below is unconditional, with clamped addresses, so that all
+  // of them are in flight together: the lane's cell byte, its staging group
+  // (a group outside the region loads a clamped one and stores nothing),
+  // then its piece, which needs the cell byte only.  A cell outside a
+  // partial block reads the block's own (unused) plan slot.
   const int cx = tid & (kDecTile / 4 - 1), cy = tid / (kDecTile / 4);
   const bool live = 4 * cx < g.bw && 4 * cy < g.bh;
-  uint32_t p = 0u;
-  uint2 pc = make_uint2(0u, 0u);
-  if (live) {
-    p = cells[(size_t)blk * kDecCells + tid];
-    pc = pieces[(size_t)blk * kDecCells + p];
-  }
+  const uint32_t p = cells[(size_t)blk * kDecCells + tid];
   // ---- stage: one 8 x 8-pixel group per lane -> 4 x 4 H0 and H0^T
-  {
-    const int gx = tid % D::NG8, gy = tid / D::NG8;
-    if (gy < g.n8y && gx < g.n8x) {
-      const int x = g.ax0 + 8 * gx;
-      uint32_t v[8][2];
+  const int gx0 = tid % D::NG8, gy0 = tid / D::NG8;
+  const bool stage = gy0 < g.n8y && gx0 < g.n8x;
+  const int gx = min(gx0, g.n8x - 1), gy = min(gy0, g.n8y - 1);
+  const int x = g.ax0 + 8 * gx;        // x < W; x + 4 == W when the group sticks out
+  const int second = x + 8 <= W ? 1 : 0;
+  uint32_t v[8][2];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        v[r][0] = v[r][1] = 0u;
-        const int y = g.ay0 + 8 * gy + r;
-        if (y < H) {
-          const uint32_t* src = reinterpret_cast<const uint32_t*>(cur + (size_t)y * W + x);
-          if (x + 8 <= W) {
-            v[r][0] = src[0];
-            v[r][1] = src[1];
-          } else if (x < W) {
-            v[r][0] = src[0];
-          }
-        }
-      }
-      uint32_t hr[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        hr[q] = mean2x2_x4(v[2 * q][0], v[2 * q][1], v[2 * q + 1][0], v[2 * q + 1][1]);
-        s_h0[(4 * gy + q) * PW + gx] = hr[q];
-      }
-      const uint32_t u0 = __builtin_amdgcn_perm(hr[1], hr[0], 0x05010400u);
-      const uint32_t u1 = __builtin_amdgcn_perm(hr[1], hr[0], 0x07030602u);
-      const uint32_t w0 = __builtin_amdgcn_perm(hr[3], hr[2], 0x05010400u);
-      const uint32_t w1 = __builtin_amdgcn_perm(hr[3], hr[2], 0x07030602u);
-      s_h0t[(4 * gx + 0) * PW + gy] = __builtin_amdgcn_perm(w0, u0, 0x05040100u);
-      s_h0t[(4 * gx + 1) * PW + gy] = __builtin_amdgcn_perm(w0, u0, 0x07060302u);
-      s_h0t[(4 * gx + 2) * PW + gy] = __builtin_amdgcn_perm(w1, u1, 0x05040100u);
-      s_h0t[(4 * gx + 3) * PW + gy] = __builtin_amdgcn_perm(w1, u1, 0x07060302u);
-    }
+  for (int r = 0; r < 8; ++r) {
+    const int y = min(g.ay0 + 8 * gy + r, H - 1);   // rows past the image feed no domain
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(cur + (size_t)y * W + x);
+    v[r][0] = src[0];
+    v[r][1] = src[second];                          // columns past the image feed no domain
   }
+  __builtin_amdgcn_sched_barrier(0);     // keep the staging loads ahead of the piece load
+  const uint2 pc = pieces[(size_t)blk * kDecCells + p];
+  uint32_t hr[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) hr[q] = mean2x2_x4(v[2 * q][0], v[2 * q][1], v[2 * q + 1][0], v[2 * q + 1][1]);
+  // a lane without a group writes the spare word past the tables (no branch,
+  // so the loads above stay ahead of everything that waits for them)
+  const int o_h0 = stage ? (4 * gy) * PW + gx : D::HS * PW;
+  const int o_h0t = stage ? (4 * gx) * PW + gy : D::HS * PW;
+  const int step = stage ? PW : 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s_h0[o_h0 + q * step] = hr[q];
+  const uint32_t u0 = __builtin_amdgcn_perm(hr[1], hr[0], 0x05010400u);
+  const uint32_t u1 = __builtin_amdgcn_perm(hr[1], hr[0], 0x07030602u);
+  const uint32_t w0 = __builtin_amdgcn_perm(hr[3], hr[2], 0x05010400u);
+  const uint32_t w1 = __builtin_amdgcn_perm(hr[3], hr[2], 0x07030602u);
+  s_h0t[o_h0t + 0 * step] = __builtin_amdgcn_perm(w0, u0, 0x05040100u);
+  s_h0t[o_h0t + 1 * step] = __builtin_amdgcn_perm(w0, u0, 0x07060302u);
+  s_h0t[o_h0t + 2 * step] = __builtin_amdgcn_perm(w1, u1, 0x05040100u);
+  s_h0t[o_h0t + 3 * step] = __builtin_amdgcn_perm(w1, u1, 0x07060302u);
   s_sd[tid] = 0u;
   __syncthreads();
   // ---- the piece's fields and this cell's place in it
@@ -471,7 +478,7 @@ hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t s
 hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint32_t h, hipStream_t s) {
   const uint64_t n = (uint64_t)w * h;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 4095) / 4096)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

@@ -119,13 +119,19 @@ def test_full_search_stream_uses_records(torch_dev, ctx):
 
 
 def test_unaligned_output_uses_records(torch_dev, ctx):
+    """A byte-aligned output (and start image) runs the per-record decoder;
+    the start copy takes its byte-wise path."""
     torch = torch_dev
     rec = random_stream(64, 32, 16, 4, 12)
+    start = np.random.default_rng(12).integers(0, 256, (32, 64)).astype(np.uint8)
+    sbuf = torch.empty(64 * 32 + 4, dtype=torch.uint8, device="cuda")
+    sbuf[3:3 + 64 * 32].copy_(torch.from_numpy(start.reshape(-1)))
     buf = torch.empty(64 * 32 + 4, dtype=torch.uint8, device="cuda")
     out = buf[1:1 + 64 * 32].view(32, 64)
-    ctx.decode(_t(torch, rec), 64, 32, 16, 2, out=out)
-    assert ctx.decode_last() == fb.FE_DECODE_RECORDS
-    np.testing.assert_array_equal(out.cpu().numpy(), odec.decode(rec, 64, 32, 16, 2))
+    for iters in (0, 2):
+        ctx.decode(_t(torch, rec), 64, 32, 16, iters, start=sbuf[3:3 + 64 * 32].view(32, 64), out=out)
+        assert ctx.decode_last() == fb.FE_DECODE_RECORDS
+        np.testing.assert_array_equal(out.cpu().numpy(), odec.decode(rec, 64, 32, 16, iters, start=start))
 
 
 @pytest.mark.slow
