@@ -267,6 +267,16 @@ __device__ __forceinline__ int lane_read(int v, int src) { return __builtin_amdg
 // runs the parent's phase 2 (Technique 1) across the four teams.  Accepted
 // ranges are written at once; failed ones are compacted (ballot prefix) into
 // the next level's parent list and their children into its range list.
+// Record slot of Morton cell `cell` of tile t (row-major in a block of GX
+// tiles per row) inside its block: one row of the block's tiles at a time,
+// and inside a row cell-major, so that the records of one cell of a tile
+// row are adjacent (the level pass writes them together) and a tile row's
+// records sit in one span (the ordering kernel reads them together).
+template <int GX>
+__device__ __forceinline__ uint32_t rec_slot(uint32_t t, int cell, int cells) {
+  return (t / GX) * (uint32_t)(GX * cells) + (uint32_t)cell * GX + t % GX;
+}
+
 template <int BMAX, int L, int GX, int GY>
 __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm) {
   using G = Geo<BMAX, L, GX, GY>;
@@ -373,7 +383,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
               const int pdx = clampi(PX - PB / 2, 0, rg.W - 2 * PB);
               const int pdy = clampi(PY - PB / 2, 0, rg.H - 2 * PB);
               const int cell = morton(pmeta);
-              a.staging[slot0 + (uint32_t)(cell * G::NT) + ((pmeta >> 16) & 0xffu)] =
+              a.staging[slot0 + rec_slot<GX>((pmeta >> 16) & 0xffu, cell, G::CELLS)] =
                   make_record(PX, PY, pdx, pdy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
               atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
             }
@@ -388,7 +398,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
             const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
             const int cell = morton(meta);
-            a.staging[slot0 + (uint32_t)(cell * G::NT) + ((meta >> 16) & 0xffu)] =
+            a.staging[slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, G::CELLS)] =
                 make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                             (int)(fit & 0xffu), 0, 0, 0);
             atomicOr(&s_mask[meta >> 16], 1ull << cell);
@@ -517,12 +527,6 @@ __global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* chunk_
   if (tid == 0) chunk_base[n] = s_carry;
 }
 
-// One workgroup per kChunkTiles consecutive tiles (global order = image,
-// then tile raster).  Stream position of a record = records of all earlier
-// tiles + rank of its Morton cell among its tile's cells.  The workgroup
-// scans its tiles' counts, then copies its contiguous output range with one
-// record per lane (coalesced writes), locating each record's tile by binary
-// search over the tile bases.
 // Images a chunk of kChunkTiles tiles can touch: every image has at least
 // 2 x 2 top tiles.
 constexpr int kChunkImgs = kChunkTiles / 4 + 1;
@@ -531,34 +535,59 @@ constexpr int kChunkImgs = kChunkTiles / 4 + 1;
 // count the records before their chunk themselves (at most 16 k masks each).
 constexpr unsigned kSmallChunks = 64;
 
+// Up to this many chunks each workgroup adds up the per-chunk counts before
+// its chunk itself (at most 4 k words) instead of a separate scan.
+constexpr unsigned kSumChunks = 4096;
+
+// Records copied per pass of a chunk.
+constexpr int kPass = 1024;
+
+// One workgroup per kChunkTiles consecutive tiles (global order = image,
+// then tile raster).  Stream position of a record = records of all earlier
+// tiles + rank of its Morton cell among its tile's cells.  One lane per
+// tile: the tile's mask, its first slot and its record count; a scan of the
+// counts gives every tile's first position.  Then, per pass of kPass
+// records, each tile lane lists the slots of its records that fall in the
+// pass (lowest cell first), and the workgroup copies the pass with one
+// record per lane (coalesced writes).  Chunks are numbered XCD-major, so
+// neighbouring chunks (which share block rows of slots) share an L2.
 __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
-                                                     const uint32_t* chunk_img, uint64_t total_tiles, int cells,
-                                                     int gx, int gy, const uint64_t* masks,
+                                                     const uint32_t* chunk_img, uint64_t total_tiles,
+                                                     uint32_t n_chunks, int cells, int gx, int gy,
+                                                     const uint64_t* masks, const uint32_t* chunk_sum,
                                                      const uint64_t* chunk_base, const uint4* staging, uint4* out,
                                                      uint64_t cap, uint64_t* offsets) {
+  static_assert(kChunkTiles == 256, "one tile per lane");
   __shared__ uint32_t s_wsum[4];
-  __shared__ uint32_t s_tbase[kChunkTiles + 1];
-  __shared__ unsigned long long s_mk[kChunkTiles];
-  __shared__ unsigned long long s_slot[kChunkTiles];   // slot of cell 0 of each tile
+  __shared__ uint32_t s_tbase[kChunkTiles];
+  __shared__ unsigned long long s_rslot[kPass];
   __shared__ unsigned long long s_tf[kChunkImgs];      // the chunk's images: first tile,
   __shared__ uint32_t s_tx[kChunkImgs], s_gx[kChunkImgs], s_wf[kChunkImgs];   // tiles / blocks per row, first block
   __shared__ unsigned long long s_red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint64_t c0 = (uint64_t)blockIdx.x * kChunkTiles;
+  const uint32_t per = (n_chunks + 7u) >> 3;
+  const uint32_t chunk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (chunk >= n_chunks) return;
+  const uint64_t c0 = (uint64_t)chunk * kChunkTiles;
   unsigned long long base;
   if (chunk_base) {
-    base = chunk_base[blockIdx.x];
+    base = chunk_base[chunk];
   } else {
-    // few chunks: the records of all earlier tiles, counted here
+    // the records of all earlier tiles, counted here: from the per-chunk
+    // counts when there are some, else (few chunks) from the masks
     unsigned long long acc = 0;
-    for (uint64_t i = (uint64_t)tid; i < c0; i += 256) acc += (unsigned long long)__popcll(masks[i]);
+    if (chunk_sum) {
+      for (uint32_t i = (uint32_t)tid; i < chunk; i += 256) acc += chunk_sum[i];
+    } else {
+      for (uint64_t i = (uint64_t)tid; i < c0; i += 256) acc += (unsigned long long)__popcll(masks[i]);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) s_red[wave] = acc;
     __syncthreads();
     base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
   }
-  const uint32_t k0 = chunk_img ? chunk_img[blockIdx.x] : 0u;
+  const uint32_t k0 = chunk_img ? chunk_img[chunk] : 0u;
   const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
   if (tid < nk) {
     const ImgDev& im = imgs[k0 + tid];
@@ -569,32 +598,25 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   }
   __syncthreads();
   const int nt = gx * gy;
-  constexpr int PER = kChunkTiles / 256;
-  uint32_t cnt[PER];
-  uint32_t tsum = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const uint64_t tile = c0 + (uint64_t)tid * PER + j;
-    unsigned long long m = 0ull, slot = 0ull;
-    if (tile < total_tiles) {
-      m = masks[tile];
-      // the tile's image: the last of the chunk's images starting at or before it
-      int k = 0;
-      while (k + 1 < nk && s_tf[k + 1] <= tile) ++k;
-      const uint32_t local = (uint32_t)(tile - s_tf[k]);
-      const uint32_t ty = local / s_tx[k], tx = local - ty * s_tx[k];
-      const uint32_t by = ty / (uint32_t)gy, bx = tx / (uint32_t)gx;
-      const uint64_t blk = (uint64_t)s_wf[k] + (uint64_t)by * s_gx[k] + bx;
-      const uint32_t t = (ty - by * (uint32_t)gy) * (uint32_t)gx + (tx - bx * (uint32_t)gx);
-      slot = blk * (uint64_t)nt * (uint64_t)cells + t;
-    }
-    s_mk[tid * PER + j] = m;
-    s_slot[tid * PER + j] = slot;
-    cnt[j] = (uint32_t)__popcll(m);
-    tsum += cnt[j];
+  const uint64_t tile = c0 + (uint64_t)tid;
+  unsigned long long m = 0ull, slot = 0ull;
+  if (tile < total_tiles) {
+    m = masks[tile];
+    // the tile's image: the last of the chunk's images starting at or before it
+    int k = 0;
+    while (k + 1 < nk && s_tf[k + 1] <= tile) ++k;
+    const uint32_t local = (uint32_t)(tile - s_tf[k]);
+    const uint32_t ty = local / s_tx[k], tx = local - ty * s_tx[k];
+    const uint32_t by = ty / (uint32_t)gy, bx = tx / (uint32_t)gx;
+    const uint64_t blk = (uint64_t)s_wf[k] + (uint64_t)by * s_gx[k] + bx;
+    // slot of cell 0 (the block's slots hold one tile row after another,
+    // each cell-major: cell c of this tile at + c * gx)
+    slot = blk * (uint64_t)nt * (uint64_t)cells + (uint64_t)(ty - by * (uint32_t)gy) * (uint64_t)(gx * cells) +
+           (tx - bx * (uint32_t)gx);
   }
-  // exclusive scan of tsum over the 256 lanes
-  uint32_t incl = tsum;
+  const uint32_t cnt = (uint32_t)__popcll(m);
+  // exclusive scan of the counts over the 256 lanes
+  uint32_t incl = cnt;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t v = __shfl_up(incl, off);
@@ -602,53 +624,47 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   }
   if (lane == 63) s_wsum[wave] = incl;
   __syncthreads();
-  uint32_t wpre = 0, total = 0;
+  uint32_t pos = incl - cnt, total = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    wpre += w < wave ? s_wsum[w] : 0u;
+    pos += w < wave ? s_wsum[w] : 0u;
     total += s_wsum[w];
   }
-  uint32_t pos = wpre + incl - tsum;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    s_tbase[tid * PER + j] = pos;
-    pos += cnt[j];
-  }
-  if (tid == 0) s_tbase[kChunkTiles] = total;
-  __syncthreads();
-  // records r = r0 + tid + 256 u (consecutive lanes, consecutive outputs):
-  // the four records' slots are located first (LDS only), then all four
-  // loads are issued unconditionally (index clamped into range), then the
-  // stores, so that the loads overlap
-  constexpr int U = 4;
-  for (uint32_t r0 = 0; r0 < total; r0 += 256 * U) {
-    uint64_t sl[U];
-    unsigned long long o[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t r = r0 + (uint32_t)(tid + 256 * u);
-      const uint32_t rr = r < total ? r : total - 1u;
-      int lo = 0, hi = kChunkTiles - 1;      // last tile with base <= rr
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_tbase[mid] <= rr) lo = mid; else hi = mid - 1;
+  s_tbase[tid] = pos;
+  for (uint32_t r0 = 0; r0 < total; r0 += kPass) {
+    // this tile's records inside [r0, r0 + kPass)
+    if (cnt && pos < r0 + kPass && pos + cnt > r0) {
+      unsigned long long mm = m;
+      uint32_t r = pos;
+      for (; r < r0; ++r) mm &= mm - 1;
+      for (; mm && r < r0 + kPass; ++r) {
+        s_rslot[r - r0] = slot + (unsigned long long)__builtin_ctzll(mm) * (unsigned long long)gx;
+        mm &= mm - 1;
       }
-      unsigned long long m = s_mk[lo];
-      for (uint32_t k = rr - s_tbase[lo]; k > 0; --k) m &= m - 1;
-      sl[u] = s_slot[lo] + (uint64_t)__builtin_ctzll(m) * (uint64_t)nt;
-      o[u] = r < total ? base + r : ~0ull;
     }
-    const uint4 v0 = staging[sl[0]], v1 = staging[sl[1]], v2 = staging[sl[2]], v3 = staging[sl[3]];
-    if (o[0] < cap) out[o[0]] = v0;
-    if (o[1] < cap) out[o[1]] = v1;
-    if (o[2] < cap) out[o[2]] = v2;
-    if (o[3] < cap) out[o[3]] = v3;
+    __syncthreads();
+    const uint32_t n = min<uint32_t>((uint32_t)kPass, total - r0);
+    // all loads first (index clamped into the pass), then the stores; named
+    // values, not an array, which the compiler would place in scratch
+    static_assert(kPass == 4 * 256, "four records per lane");
+    const uint32_t ra = (uint32_t)tid, rb = ra + 256u, rc = ra + 512u, rd = ra + 768u;
+    const uint4 va = staging[s_rslot[ra < n ? ra : n - 1u]];
+    const uint4 vb = staging[s_rslot[rb < n ? rb : n - 1u]];
+    const uint4 vc = staging[s_rslot[rc < n ? rc : n - 1u]];
+    const uint4 vd = staging[s_rslot[rd < n ? rd : n - 1u]];
+    const unsigned long long o = base + r0 + ra;
+    if (ra < n && o < cap) out[o] = va;
+    if (rb < n && o + 256u < cap) out[o + 256u] = vb;
+    if (rc < n && o + 512u < cap) out[o + 512u] = vc;
+    if (rd < n && o + 768u < cap) out[o + 768u] = vd;
+    __syncthreads();
   }
+  __syncthreads();
   for (uint32_t k = tid; k < n_imgs; k += 256) {
     const uint64_t tf = imgs[k].tile_first;
     if (tf >= c0 && tf < c0 + kChunkTiles) offsets[k] = base + s_tbase[tf - c0];
   }
-  if (blockIdx.x == gridDim.x - 1 && tid == 0) offsets[n_imgs] = base + total;
+  if (chunk == n_chunks - 1 && tid == 0) offsets[n_imgs] = base + total;
 }
 
 }  // namespace
@@ -708,16 +724,26 @@ hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* c
                           uint64_t* chunk_base, const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
                           hipStream_t s) {
   const unsigned grid = (unsigned)((total_tiles + kChunkTiles - 1) / kChunkTiles);
+  const unsigned sgrid = 8u * ((grid + 7u) >> 3);     // XCD-major chunk numbering
   if (grid <= kSmallChunks) {
-    // one kernel: each chunk counts the records before it itself
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, cells,
-                       shape.gx, shape.gy, masks, (const uint64_t*)nullptr, staging, out, cap, offsets);
+    // one kernel: each chunk counts the records before it from the masks
+    hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
+                       cells, shape.gx, shape.gy, masks, (const uint32_t*)nullptr, (const uint64_t*)nullptr,
+                       staging, out, cap, offsets);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(kChunkTiles), 0, s, masks, total_tiles, chunk_sum);
+  if (grid <= kSumChunks) {
+    // each chunk adds up the counts of the chunks before it
+    hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
+                       cells, shape.gx, shape.gy, masks, (const uint32_t*)chunk_sum, (const uint64_t*)nullptr,
+                       staging, out, cap, offsets);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, chunk_sum, grid, chunk_base);
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, cells,
-                     shape.gx, shape.gy, masks, chunk_base, staging, out, cap, offsets);
+  hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
+                     cells, shape.gx, shape.gy, masks, (const uint32_t*)nullptr, (const uint64_t*)chunk_base,
+                     staging, out, cap, offsets);
   return hipGetLastError();
 }
 

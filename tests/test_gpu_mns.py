@@ -209,6 +209,21 @@ def test_encode_c3_full(torch_dev, ctx):
     assert_same_stream(got, want)
 
 
+@pytest.mark.parametrize("H,W,b_max,b_min,thr,path", [
+    (1024, 2048, 8, 4, [400], "per-chunk sums (128 chunks)"),
+    (4096, 4160, 4, 4, [], "scan kernel (4160 chunks)"),
+])
+def test_ordering_paths(torch_dev, ctx, H, W, b_max, b_min, thr, path):
+    """The ordering takes one kernel up to 64 chunks of 256 tiles (every
+    other test image), chunk counts summed by each workgroup up to 4096, and
+    a separate scan beyond; the stream is the same on each."""
+    log(f"encode {H}x{W} b{b_max}/{b_min}: {path}")
+    img = synth.noise_1f(H, W, 77 + b_max)
+    want = mns.encode(img, b_max, b_min, thr)
+    got = gpu_stream(torch_dev, ctx, img, b_max, b_min, thr)
+    assert_same_stream(got, want)
+
+
 # ------------------------------------------------------------------ batch
 def test_encode_batch_matches_single(torch_dev, ctx):
     rng = np.random.default_rng(5)
