@@ -542,6 +542,27 @@ constexpr unsigned kSumChunks = 4096;
 // Records copied per pass of a chunk.
 constexpr int kPass = 1024;
 
+// Per-lane share (of 256 lanes) of the record counts in p[0, n): 16 loads
+// in flight per round, addresses clamped, so that no load waits for the one
+// before it.
+__device__ __forceinline__ uint64_t count_of(uint32_t v) { return v; }
+__device__ __forceinline__ uint64_t count_of(uint64_t mask) { return (uint64_t)__popcll(mask); }
+template <typename T>
+__device__ __forceinline__ unsigned long long lane_sum(const T* p, uint64_t n, int tid) {
+  unsigned long long acc = 0;
+  for (uint64_t i0 = 0; i0 < n; i0 += 256u * 16u) {
+    T x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const uint64_t i = i0 + (uint64_t)tid + 256u * (uint64_t)u;
+      x[u] = p[i < n ? i : n - 1u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += i0 + (uint64_t)tid + 256u * (uint64_t)u < n ? count_of(x[u]) : 0u;
+  }
+  return acc;
+}
+
 // One workgroup per kChunkTiles consecutive tiles (global order = image,
 // then tile raster).  Stream position of a record = records of all earlier
 // tiles + rank of its Morton cell among its tile's cells.  One lane per
@@ -569,39 +590,38 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   const uint32_t chunk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   if (chunk >= n_chunks) return;
   const uint64_t c0 = (uint64_t)chunk * kChunkTiles;
+  // independent loads first: this lane's tile mask and image entry
+  const uint64_t tile = c0 + (uint64_t)tid;
+  const bool has_tile = tile < total_tiles;
+  const unsigned long long m_raw = masks[has_tile ? tile : 0u];
+  const uint32_t k0 = chunk_img ? chunk_img[chunk] : 0u;
+  const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
+  const ImgDev im = imgs[k0 + (uint32_t)min(tid, nk - 1)];
   unsigned long long base;
   if (chunk_base) {
     base = chunk_base[chunk];
   } else {
     // the records of all earlier tiles, counted here: from the per-chunk
     // counts when there are some, else (few chunks) from the masks
-    unsigned long long acc = 0;
-    if (chunk_sum) {
-      for (uint32_t i = (uint32_t)tid; i < chunk; i += 256) acc += chunk_sum[i];
-    } else {
-      for (uint64_t i = (uint64_t)tid; i < c0; i += 256) acc += (unsigned long long)__popcll(masks[i]);
-    }
+    unsigned long long acc = chunk_sum ? lane_sum(chunk_sum, (uint64_t)chunk, tid)
+                                       : lane_sum(masks, c0, tid);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) s_red[wave] = acc;
-    __syncthreads();
-    base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    base = 0;   // read after the barrier below
   }
-  const uint32_t k0 = chunk_img ? chunk_img[chunk] : 0u;
-  const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
   if (tid < nk) {
-    const ImgDev& im = imgs[k0 + tid];
     s_tf[tid] = im.tile_first;
     s_tx[tid] = im.tiles_x;
     s_gx[tid] = im.groups_x;
     s_wf[tid] = im.wg_first;
   }
   __syncthreads();
+  if (!chunk_base) base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
   const int nt = gx * gy;
-  const uint64_t tile = c0 + (uint64_t)tid;
   unsigned long long m = 0ull, slot = 0ull;
-  if (tile < total_tiles) {
-    m = masks[tile];
+  if (has_tile) {
+    m = m_raw;
     // the tile's image: the last of the chunk's images starting at or before it
     int k = 0;
     while (k + 1 < nk && s_tf[k + 1] <= tile) ++k;
