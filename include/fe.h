@@ -406,6 +406,14 @@ void fe_server_destroy(fe_server* server);
 
 fe_status fe_timing_enable(fe_ctx* ctx, int enable);
 fe_status fe_timing_read(fe_ctx* ctx, double* ms, uint64_t* launches, uint32_t n);
+/*
+ * Which slots are timed while timing is on: bit k of slot_mask for slot k
+ * (default: all).  Each timed launch costs two event records on the GPU
+ * (a few microseconds each), so a caller that needs one kernel's time can
+ * leave the others untimed.  Applies to eager launches; a recorded plan
+ * created with timing on times its encode and ordering kernels.
+ */
+fe_status fe_timing_select(fe_ctx* ctx, uint32_t slot_mask);
 
 #ifdef __cplusplus
 }

@@ -96,6 +96,7 @@ _SIGNATURES = {
                                    _VP, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32),
                                    ctypes.POINTER(ctypes.c_double), _VP]),
     "fe_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "fe_timing_select": (ctypes.c_int, [_VP, _U32]),
     "fe_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                       _U32]),
 }
@@ -350,6 +351,11 @@ def fe_autotune(ctx: int, imgs, params: fe_params, out, offsets, reps: int = 3, 
                               _ptr(offsets), reps, ctypes.byref(gx), ctypes.byref(gy), ctypes.byref(ms),
                               _stream(stream)))
     return (gx.value, gy.value), ms.value
+
+
+def fe_timing_select(ctx: int, slot_mask: int) -> None:
+    """Time only the slots whose bits are set (default: all)."""
+    _check(load().fe_timing_select(ctx, slot_mask))
 
 
 def fe_timing_enable(ctx: int, enable: bool = True) -> None:

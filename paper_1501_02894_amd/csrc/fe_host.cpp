@@ -69,6 +69,7 @@ struct fe_ctx {
   fe::TileShape shape_override[33][5] = {};
   // kernel timing (fe_timing_enable)
   bool timing = false;
+  uint32_t timing_mask = ~0u;         // slots timed while timing is on (fe_timing_select)
   static constexpr int kTimingCap = 4096;
   hipEvent_t* ev = nullptr;           // 2 * kTimingCap events
   int ev_slot[kTimingCap] = {};
@@ -147,7 +148,7 @@ struct Timed {
   hipStream_t s;
   int idx = -1;
   Timed(fe_ctx* ctx, int slot, hipStream_t stream) : c(ctx), s(stream) {
-    if (!c->timing || !c->ev || c->ev_used >= fe_ctx::kTimingCap) return;
+    if (!c->timing || !c->ev || c->ev_used >= fe_ctx::kTimingCap || !((c->timing_mask >> slot) & 1u)) return;
     idx = c->ev_used++;
     c->ev_slot[idx] = slot;
     (void)hipEventRecord(c->ev[2 * idx], s);
@@ -746,6 +747,13 @@ fe_status fe_timing_enable(fe_ctx* ctx, int enable) {
       FE_HIP(hipEventCreate(&ctx->ev[i]), "timing events");
   }
   ctx->timing = enable != 0;
+  return FE_OK;
+}
+
+fe_status fe_timing_select(fe_ctx* ctx, uint32_t slot_mask) {
+  fe::clear_error();
+  if (!ctx) return fe::fail(FE_ERR_INVALID, "NULL context");
+  ctx->timing_mask = slot_mask;
   return FE_OK;
 }
 

@@ -98,3 +98,6 @@ def test_null_arguments(lib):
     assert lib.fe_encode(None, None, 64, 64, 64, ctypes.byref(p), None, 0, ctypes.byref(n), None) == fb.FE_ERR_INVALID
     assert lib.fe_decode(None, None, 0, 64, 64, 16, 1, None, None, None) == fb.FE_ERR_INVALID
     lib.fe_destroy(None)
+    assert lib.fe_timing_select(None, 1) == fb.FE_ERR_INVALID
+    assert lib.fe_decode_set_mode(None, 0) == fb.FE_ERR_INVALID
+    assert lib.fe_decode_last(None) == fb.FE_DECODE_RECORDS

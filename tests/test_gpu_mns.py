@@ -310,6 +310,27 @@ def test_plan_replays_match_eager(torch_dev, ctx):
         fb.fe_timing_enable(ctx.handle, False)
 
 
+def test_timing_select(torch_dev, ctx):
+    """fe_timing_select limits the timed launches to the chosen slots."""
+    img = dev(torch_dev, synth.workload("c2"))
+    fb.fe_timing_read(ctx.handle)
+    try:
+        for mask, want in ((1 << fb.FE_TIMING_ENCODE, (2, 0)), (1 << fb.FE_TIMING_SCATTER, (0, 2)),
+                           (0xffffffff, (2, 2))):
+            fb.fe_timing_select(ctx.handle, mask)
+            fb.fe_timing_enable(ctx.handle, True)
+            for _ in range(2):
+                ctx.encode(img, 16, 4, [300, 200])
+            torch_dev.cuda.synchronize()
+            fb.fe_timing_enable(ctx.handle, False)
+            ms, cnt = fb.fe_timing_read(ctx.handle)
+            assert (cnt[fb.FE_TIMING_ENCODE], cnt[fb.FE_TIMING_SCATTER]) == want
+            assert all(ms[k] > 0 for k in (fb.FE_TIMING_ENCODE, fb.FE_TIMING_SCATTER) if cnt[k])
+    finally:
+        fb.fe_timing_select(ctx.handle, 0xffffffff)
+        fb.fe_timing_enable(ctx.handle, False)
+
+
 # ------------------------------------------------------------------ decode
 @pytest.mark.parametrize("name,b_max,b_min,thr,iters", [
     ("c1", 8, 4, [600], 12),
