@@ -576,7 +576,7 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
   // Tile-ordered decoding needs whole top tiles, room for a domain of the
   // top size, word-aligned rows and a stream that partitions every tile in
   // stream order with co-centred domains (checked on the device below).
-  const bool tiled_shape = ctx->decode_mode == FE_DECODE_AUTO && n > 0 && w % b_max == 0 && h % b_max == 0 && w >= 2 * b_max && h >= 2 * b_max &&
+  bool tiled_shape = ctx->decode_mode == FE_DECODE_AUTO && n > 0 && w % b_max == 0 && h % b_max == 0 && w >= 2 * b_max && h >= 2 * b_max &&
                            ((uintptr_t)d_out & 3) == 0;
   const size_t ntiles = (size_t)(w / b_max) * (h / b_max);
   const size_t nblk = fe::decode_plan_blocks(w, h);
@@ -584,7 +584,12 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
     fe_status st = ensure(ctx->dec_tiles, ctx->dec_tiles_n, ntiles + 1, "tile starts");
     if (st == FE_OK) st = ensure(ctx->dec_cells, ctx->dec_cells_n, nblk * 256, "decode plan cells");
     if (st == FE_OK) st = ensure(ctx->dec_pieces, ctx->dec_pieces_n, nblk * 256, "decode plan pieces");
-    if (st != FE_OK) return st;
+    if (st != FE_OK) {
+      // no room for the plan: the per-record decoder needs none
+      (void)hipGetLastError();
+      fe::clear_error();
+      tiled_shape = false;
+    }
   }
   FE_HIP(fe::launch_zero_u32(ctx->flags, 2, s), "zero flags");
   FE_HIP(fe::launch_decode_check(a, ctx->flags, s), "check launch");
