@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_DOT4_TMACS = 1024 * 16 * 4 * 2.4e9 / 1e12   # 157.3
 B_MAX, B_MIN, THR = 16, 4, (300, 200)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mns_tiles_c4_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1501_02894_amd", "csrc", f)
@@ -56,32 +57,40 @@ def _gen_one(k):
     return synth._mixed_image(side, kind, ss)
 
 
-def range_blocks(level, flags, tiles: int, n_levels: int) -> int:
-    """Phase-1 evaluations of quadtree streams, Sum_l |W_l|, from their
-    records' levels and flags: W_1 holds the top tiles, and the level-l
-    ranges accepted by neither phase are split, their four children forming
-    W_l+1 (a phase-2 record stands for its level-l range).  The fused kernel
-    also fits the children of ranges that phase 2 accepts, which is extra
-    work of this design and not counted."""
-    level = np.asarray(level).astype(np.int64)
-    p = np.bincount(level, minlength=n_levels)     # records (either phase) per level
-    R, total = int(tiles), 0
+def level_sizes(level, tiles: int, n_levels: int) -> list:
+    """|W_l| per level of quadtree streams, from their records' levels: W_1
+    holds the top tiles, and the level-l ranges accepted by neither phase
+    are split, their four children forming W_l+1 (a phase-2 record stands
+    for its level-l range).  The fused kernel also fits the children of
+    ranges that phase 2 accepts, which is extra work of this design and not
+    counted."""
+    p = np.bincount(np.asarray(level).astype(np.int64), minlength=n_levels)   # records per level
+    R, sizes = int(tiles), []
     for lv in range(n_levels):
-        total += R
+        sizes.append(R)
         split = R - int(p[lv])
         assert split >= 0 and (split == 0 or lv < n_levels - 1)
         R = 4 * split
-    return total
+    return sizes
+
+
+def range_blocks(level, flags, tiles: int, n_levels: int) -> int:
+    """Phase-1 evaluations, Sum_l |W_l| (flags: unused, kept for callers that
+    pass whole records)."""
+    return sum(level_sizes(level, tiles, n_levels))
 
 
 def n_levels(b_max: int, b_min: int) -> int:
     return (b_max // b_min).bit_length()
 
 
+def gpu_level_sizes(out, n: int, tiles: int, b_max: int, b_min: int) -> list:
+    """level_sizes of the first n records of a device record array."""
+    return level_sizes(out[:n, 8].cpu().numpy(), tiles, n_levels(b_max, b_min))
+
+
 def gpu_range_blocks(out, n: int, tiles: int, b_max: int, b_min: int) -> int:
-    """range_blocks of the first n records of a device record array."""
-    head = out[:n, 8:10].cpu().numpy()
-    return range_blocks(head[:, 0], head[:, 1], tiles, n_levels(b_max, b_min))
+    return sum(gpu_level_sizes(out, n, tiles, b_max, b_min))
 
 
 def cpu_baseline(images, budget_s: float):
@@ -386,7 +395,11 @@ def main():
     off_h = offsets.cpu().numpy()
     n_rec = int(off_h[-1])
     per_img = np.diff(off_h)
-    blocks = gpu_range_blocks(out, n_rec, sum(tiles), B_MAX, B_MIN)
+    sizes = gpu_level_sizes(out, n_rec, sum(tiles), B_MAX, B_MIN)
+    blocks = sum(sizes)
+    # algorithmic int8 multiply-adds of the moments: per B x B range, Sum r,
+    # Sum r^2, Sum d, Sum d^2 and the 8 isometric Sum r T_e(d), B^2 each
+    macs = sum(12 * (B_MAX >> lv) ** 2 * r for lv, r in enumerate(sizes))
     value = blocks / (ms_per_step / 1e3)
 
     # the same step recorded once as a HIP graph and replayed (untimed)
@@ -462,7 +475,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "mns_tiles_kernel<16,3>", "kernel_ms": enc_ms,
-                     "algorithmic_bytes": alg_bytes},
+                     "algorithmic_bytes": alg_bytes,
+                     # the same launch against the vector ALU: packed-u8 dot
+                     # products, 1024 SIMDs x 16 lanes x 4 MACs x 2.4 GHz
+                     "alu": {"int8_macs": macs, "achieved": macs / (enc_ms / 1e3) / 1e12,
+                             "peak": VALU_DOT4_TMACS, "unit": "TMAC/s",
+                             "frac": macs / (enc_ms / 1e3) / 1e12 / VALU_DOT4_TMACS}},
         "images_per_s": len(images) / (ms_per_step / 1e3),
         "pipelined": {"ms_per_step": pipe_ms, "range_blocks_per_s": blocks / (pipe_ms / 1e3),
                       "batches_in_flight": 2, "same_stream": pipe_same},
