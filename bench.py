@@ -217,10 +217,13 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     arrivals = np.cumsum(rng.exponential(1.0 / rate, total))
     which = rng.integers(0, len(pool), total)
     done_at = np.zeros(total)
-    t0 = time.perf_counter() + 0.05
     if mode == "server":
+        # the server is long-lived: created (arenas allocated) before the
+        # arrival clock starts
         srv = fb.Server(B_MAX, B_MIN, THR, hbm_budget=16 << 30, host_budget=4 << 30, max_slots=512,
                         step_blocks=2048)
+    t0 = time.perf_counter() + 0.05
+    if mode == "server":
         lat = np.zeros(total)
         index = {}
 
@@ -315,7 +318,8 @@ def main():
     ap.add_argument("--images", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the plain/cold comparisons")
+    ap.add_argument("--no-extras", action="store_true", help="skip the comparisons (plain, cold, two batches in flight) and the "
+                                                             "single-image, decode and full-search runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for counter scaling)")
     ap.add_argument("--serve-rates", default="500,2000,8000,20000,40000")
@@ -415,29 +419,33 @@ def main():
     graph_same = bool(np.array_equal(offsets.cpu().numpy(), off_h))
     plan.close()
 
-    # two batches in flight: consecutive steps alternate between two
-    # contexts on two streams, so one batch's ordering overlaps the next
-    # batch's encode (untimed kernels; whole-job throughput)
-    ctx2 = fb.Context(0)
-    out2 = torch.empty_like(out)
-    offsets2 = torch.zeros_like(offsets)
-    streams = (torch.cuda.Stream(), torch.cuda.Stream())
-    lanes = ((ctx, out, offsets), (ctx2, out2, offsets2))
+    pipelined = None
+    if not args.no_extras:
+        # two batches in flight: consecutive steps alternate between two
+        # contexts on two streams, so one batch's ordering overlaps the next
+        # batch's encode (untimed kernels; whole-job throughput)
+        ctx2 = fb.Context(0)
+        out2 = torch.empty_like(out)
+        offsets2 = torch.zeros_like(offsets)
+        streams = (torch.cuda.Stream(), torch.cuda.Stream())
+        lanes = ((ctx, out, offsets), (ctx2, out2, offsets2))
 
-    def pstep(i):
-        c, o, f = lanes[i & 1]
-        fb.fe_encode_batch(c.handle, views, params, out=o, offsets=f, wait=False, descs=descs, stream=streams[i & 1])
+        def pstep(i):
+            c, o, f = lanes[i & 1]
+            fb.fe_encode_batch(c.handle, views, params, out=o, offsets=f, wait=False, descs=descs, stream=streams[i & 1])
 
-    for i in range(max(2, args.warmup)):
-        pstep(i)
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    for i in range(args.steps):
-        pstep(i)
-    torch.cuda.synchronize()
-    pipe_ms = (time.perf_counter() - p0) * 1e3 / args.steps
-    pipe_same = bool(np.array_equal(offsets2.cpu().numpy(), off_h)) and bool(torch.equal(out2[:n_rec], out[:n_rec]))
-    ctx2.close()
+        for i in range(max(2, args.warmup)):
+            pstep(i)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for i in range(args.steps):
+            pstep(i)
+        torch.cuda.synchronize()
+        pipe_ms = (time.perf_counter() - p0) * 1e3 / args.steps
+        pipe_same = bool(np.array_equal(offsets2.cpu().numpy(), off_h)) and bool(torch.equal(out2[:n_rec], out[:n_rec]))
+        ctx2.close()
+        pipelined = {"ms_per_step": pipe_ms, "range_blocks_per_s": blocks / (pipe_ms / 1e3),
+                     "batches_in_flight": 2, "same_stream": pipe_same}
 
     enc_ms = kms[fb.FE_TIMING_ENCODE] / max(1, kcnt[fb.FE_TIMING_ENCODE])
     sc_ms = sms[fb.FE_TIMING_SCATTER] / max(1, scnt[fb.FE_TIMING_SCATTER])
@@ -482,8 +490,7 @@ def main():
                              "peak": VALU_DOT4_TMACS, "unit": "TMAC/s",
                              "frac": macs / (enc_ms / 1e3) / 1e12 / VALU_DOT4_TMACS}},
         "images_per_s": len(images) / (ms_per_step / 1e3),
-        "pipelined": {"ms_per_step": pipe_ms, "range_blocks_per_s": blocks / (pipe_ms / 1e3),
-                      "batches_in_flight": 2, "same_stream": pipe_same},
+        "pipelined": pipelined,
         "graph": {"ms_per_step": graph_ms, "range_blocks_per_s": blocks / (graph_ms / 1e3),
                   "same_offsets": graph_same},
         "scatter_ms": sc_ms,

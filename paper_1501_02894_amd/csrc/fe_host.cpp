@@ -748,8 +748,10 @@ fe_status fe_timing_enable(fe_ctx* ctx, int enable) {
   DeviceGuard g(ctx->device);
   if (enable && !ctx->ev) {
     ctx->ev = new hipEvent_t[2 * fe_ctx::kTimingCap]();
+    // timestamps only: no system-scope fence (cache writeback) when an
+    // event completes, which would add to the bracketed kernel's time
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
-      FE_HIP(hipEventCreate(&ctx->ev[i]), "timing events");
+      FE_HIP(hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableSystemFence), "timing events");
   }
   ctx->timing = enable != 0;
   return FE_OK;
