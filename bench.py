@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--decode-only", action="store_true",
                     help="only decode C3 (4096^2, 32 -> 4) with both decoders (a profiling workload)")
+    ap.add_argument("--fullsearch-only", action="store_true",
+                    help="only the exhaustive-search encode of C2 (512^2, 16 -> 4) (a profiling workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -340,6 +342,14 @@ def main():
     dev = torch.device("cuda:0")
     if args.decode_only:
         decode_only(fb, args)
+        return
+    if args.fullsearch_only:
+        from paper_1501_02894_amd import synth
+        ctx = fb.Context(0)
+        res = bench_fullsearch(fb, ctx, synth.workload("c2"), 16, 4, [300, 200], reps=args.steps)
+        ctx.close()
+        print(json.dumps({"workload": "c2 exhaustive search (512^2, 16 -> 4, thresholds 300,200)",
+                          "c2_fullsearch": res}), flush=True)
         return
     t_gen = time.perf_counter()
     images, _ = gen_images(args.images)
