@@ -316,13 +316,15 @@ def _records(n: int) -> np.ndarray:
 
 
 def encode(img: np.ndarray, b_max: int, b_min: int, thresholds, phase2: bool = True,
-           trace: list | None = None) -> np.ndarray:
+           trace: list | None = None, isometries: bool = True) -> np.ndarray:
     """MNS encoder: the record stream of ``img`` (uint8, H x W) in stream order.
 
     ``thresholds`` holds the integer MSE threshold of levels 1..L-1.  With
-    ``phase2`` False this is the plain no-search coder of Sec. 3.  If
-    ``trace`` is a list, one dict per level is appended with that level's
-    worklist, moments, fit and decisions.
+    ``phase2`` False this is the plain no-search coder of Sec. 3.  With
+    ``isometries`` False phase 1 fits the identity only (the paper's 14-bit
+    phase-1 code of Sec. 3.3 stores no isometry).  If ``trace`` is a list,
+    one dict per level is appended with that level's worklist, moments, fit
+    and decisions.
     """
     img = np.asarray(img)
     if img.dtype != np.uint8 or img.ndim != 2:
@@ -341,6 +343,9 @@ def encode(img: np.ndarray, b_max: int, b_min: int, thresholds, phase2: bool = T
         B = b_max >> (level - 1)
         n = B * B
         mom = range_moments(I, h0, xs, ys, B)
+        if not isometries:
+            # every isometry scores as the identity, so the first (e = 0) wins
+            mom = dict(mom, srd=np.repeat(mom["srd"][:, :1], 8, axis=1))
         e, k, m, S = fit_phase1(mom, n)
         last = level == L
         if last:

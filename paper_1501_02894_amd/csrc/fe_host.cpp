@@ -323,6 +323,7 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
   a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
   for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
   a.staging = ctx->staging;
   a.masks = ctx->masks;
@@ -895,6 +896,7 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   a.n_imgs = n_imgs;
   a.n_wg = wgs;
   a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
   for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
   a.staging = pl->staging;
   a.masks = pl->masks;

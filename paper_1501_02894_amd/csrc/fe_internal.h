@@ -37,7 +37,7 @@ struct EncodeArgs {
   uint32_t n_imgs;
   uint32_t n_wg;       // logical workgroups over all images
   uint32_t phase2;     // run Technique 1
-  uint32_t pad;
+  uint32_t identity_only;   // phase 1 fits the identity isometry only
   uint32_t thr[4];     // MSE thresholds of levels 1..L-1
   // Record slots, one group of NT * cells per workgroup block (NT tiles),
   // cell-major inside it: the record of Morton cell c of the block's tile t

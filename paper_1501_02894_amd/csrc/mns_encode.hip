@@ -341,6 +341,10 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
                                              G::HP, s_h0t, wx * G::TP + wy, G::TP, i, acc);
         }
         team_reduce(acc, T);   // butterfly: every lane of the team holds the totals
+        if (a.identity_only) {  // every isometry scores as the identity: the fit keeps e = 0
+#pragma unroll
+          for (int j = 5; j < 12; ++j) acc[j] = acc[4];
+        }
         const uint32_t fit = fit_phase1<BB>(acc, last, thr);
 
         // ---- phase 2 of the parent of this group of four children

@@ -319,6 +319,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     a.n_imgs = 1;
     a.n_wg = n;
     a.phase2 = (s->params.flags & FE_PHASE2) ? 1u : 0u;
+    a.identity_only = (s->params.flags & FE_IDENTITY_ONLY) ? 1u : 0u;
     for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)s->params.n_thr ? s->params.mse_thr[l] : 0u;
     a.staging = s->staging;
     a.masks = s->masks;

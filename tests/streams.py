@@ -16,7 +16,10 @@ from oracle import mns
 
 
 def random_stream(width: int, height: int, b_max: int, b_min: int, seed: int,
-                  p_split: float = 0.5, p_phase2: float = 0.3) -> np.ndarray:
+                  p_split: float = 0.5, p_phase2: float = 0.3, bounded: bool = False) -> np.ndarray:
+    """With ``bounded`` the phase-2 differences O_c - O_i (all four, O_3 from
+    eq. (1)) stay within the bound Technique 1 accepts, +-15 at level 1 and
+    +-31 below, so that the stream fits the stored widths of Sec. 3.3."""
     rng = np.random.default_rng(seed)
     out = []
 
@@ -25,9 +28,15 @@ def random_stream(width: int, height: int, b_max: int, b_min: int, seed: int,
         r["x"], r["y"], r["level"] = x, y, level
         if B >= 8 and level <= 2 and rng.random() < p_phase2:
             m = int(rng.integers(40, 216))
-            d = rng.integers(-40, 41, size=3)
-            s01 = int(d[0] + d[1])     # O_2 = m + d_2 and O_3 = m - (d_0 + d_1 + d_2) both in 0..255
-            d[2] = int(np.clip(d[2], max(-s01 - 40, -m), min(-s01 + 40, 255 - m)))
+            if bounded:
+                delta = mns.PHASE2_DELTA[level + 1]
+                d = rng.integers(-delta, delta + 1, size=3)
+                s01 = int(d[0] + d[1])   # d_2 and O_3 - m = -(d_0 + d_1 + d_2) both within +-delta
+                d[2] = int(np.clip(d[2], max(-s01 - delta, -delta), min(-s01 + delta, delta)))
+            else:
+                d = rng.integers(-40, 41, size=3)
+                s01 = int(d[0] + d[1])   # O_2 = m + d_2 and O_3 = m - (d_0 + d_1 + d_2) both in 0..255
+                d[2] = int(np.clip(d[2], max(-s01 - 40, -m), min(-s01 + 40, 255 - m)))
             r["flags"] = mns.FLAG_PHASE2
             r["s_idx"] = int(rng.integers(0, 16))
             r["lum"] = m

@@ -1,0 +1,184 @@
+"""Pins of the bitstream oracle (Sec. 3.3, Sec. 3.4), CPU only.
+
+* the code sizes the paper prints: 14 bits per phase-1 block, and a phase-2
+  block of 1 + 2 + 8 + 3 M + 4 bits with M = 5 at level 1 and 6 below;
+* Technique 2's level-bit count, checked against the paper's two worked
+  figures (4000 last-level blocks: 8000 -> 2000 bits; 25000: 6.25 KB ->
+  about 1.5 KB);
+* two small streams whose bits are spelled out field by field here, from
+  the field list of the layout (not through the oracle's writer);
+* pack -> unpack returns every record unchanged, on encoded and random
+  streams with every record kind;
+* planted mistakes (no level elision, two's-complement differences) fail
+  the spelled-out streams.
+"""
+import numpy as np
+import pytest
+
+from oracle import bitstream as bs
+from oracle import mns
+from paper_1501_02894_amd import synth
+from streams import random_stream
+
+
+def lsb(value: int, width: int) -> str:
+    """`value` as `width` bits, least significant first."""
+    return "".join(str((value >> b) & 1) for b in range(width))
+
+
+def to_bytes(bits: str) -> bytes:
+    out = bytearray((len(bits) + 7) // 8)
+    for p, c in enumerate(bits):
+        if c == "1":
+            out[p // 8] |= 1 << (p % 8)
+    return bytes(out)
+
+
+def header(W, H, b_max, b_min, iso):
+    return (lsb(W - 1, 16) + lsb(H - 1, 16) + lsb(b_max.bit_length() - 1, 3) + lsb(b_min.bit_length() - 1, 3) +
+            lsb(1 if iso else 0, 1) + "0" * 25)
+
+
+def rec(x, y, level, lum, s_idx, iso=0, flags=0, dlum=(0, 0, 0), W=16, H=16, b_max=8):
+    r = np.zeros((), mns.RECORD_DTYPE)
+    B = b_max >> level
+    r["x"], r["y"], r["level"], r["lum"], r["s_idx"], r["iso"], r["flags"] = x, y, level, lum, s_idx, iso, flags
+    r["dx"] = int(mns.domain_origin(x, B, W))
+    r["dy"] = int(mns.domain_origin(y, B, H))
+    r["dlum"] = dlum
+    return r
+
+
+def tiny_phase1():
+    """8 x 8 image, 4 x 4 tiles only (one level, no elision), isometries on."""
+    vals = [(0xA5, 3, 5), (1, 7, 0), (255, 0, 7), (128, 1, 2)]
+    recs = [rec(4 * (t % 2), 4 * (t // 2), 0, lum, k, iso=e, W=8, H=8, b_max=4) for t, (lum, k, e) in enumerate(vals)]
+    bits = header(8, 8, 4, 4, True)
+    for lum, k, e in vals:
+        bits += "0" + lsb(0, 2) + lsb(lum, 8) + lsb(k, 3) + lsb(e, 3)
+    return np.array(recs, mns.RECORD_DTYPE), bits
+
+
+def tiny_mixed():
+    """16 x 16 image, 8 -> 4: tile 0 a phase-2 block, tile 1 split into four
+    last-level blocks (the last three without level bits), tiles 2 and 3
+    phase-1 blocks; identity only (the paper's 14-bit phase-1 code)."""
+    recs = [
+        rec(0, 0, 0, 100, 0b1010, flags=1, dlum=(-3, 15, 0)),
+        rec(8, 0, 1, 10, 1), rec(12, 0, 1, 20, 2), rec(8, 4, 1, 30, 3), rec(12, 4, 1, 40, 4),
+        rec(0, 8, 0, 50, 5), rec(8, 8, 0, 60, 6),
+    ]
+    bits = header(16, 16, 8, 4, False)
+    # phase 2 at level 1 (M = 5): sign bit, then 4 magnitude bits
+    bits += "1" + lsb(0, 2) + lsb(100, 8) + ("1" + lsb(3, 4)) + ("0" + lsb(15, 4)) + ("0" + lsb(0, 4)) + lsb(0b1010, 4)
+    bits += "0" + lsb(1, 2) + lsb(10, 8) + lsb(1, 3)            # first child: level stored
+    for lum, k in ((20, 2), (30, 3), (40, 4)):                   # its siblings: no level (Technique 2)
+        bits += "0" + lsb(lum, 8) + lsb(k, 3)
+    for lum, k in ((50, 5), (60, 6)):
+        bits += "0" + lsb(0, 2) + lsb(lum, 8) + lsb(k, 3)
+    return np.array(recs, mns.RECORD_DTYPE), bits
+
+
+def _check_tiny(maker, W, H, b_max, b_min, iso):
+    recs, bits = maker()
+    got, nbits = bs.pack(recs, W, H, b_max, b_min, isometries=iso)
+    assert nbits == len(bits)
+    assert got == to_bytes(bits)
+    back = bs.unpack(to_bytes(bits), len(bits))
+    assert back[1:] == (W, H, b_max, b_min, iso)
+    assert back[0].tobytes() == recs.tobytes()
+
+
+def test_tiny_phase1_bits():
+    _check_tiny(tiny_phase1, 8, 8, 4, 4, True)
+
+
+def test_tiny_mixed_bits():
+    _check_tiny(tiny_mixed, 16, 16, 8, 4, False)
+
+
+def test_code_sizes_printed_by_the_paper():
+    # phase 1: luminance byte + 3 contrast bits + phase bit + 2 level bits = 14 (Sec. 3.3)
+    one = np.array([rec(0, 0, 0, 7, 1)], mns.RECORD_DTYPE)
+    assert int(bs.code_lengths(one, 8, 4, isometries=False)[0]) == 14
+    assert int(bs.code_lengths(one, 8, 4, isometries=True)[0]) == 17
+    # phase 2: 1 + 2 + 8 + 3 M + 4 with M = 5 at level 1, 6 at levels 2 and 3
+    for level, M in ((0, 5), (1, 6), (2, 6)):
+        r = np.array([rec(0, 0, level, 7, 3, flags=1, W=64, H=64, b_max=32)], mns.RECORD_DTYPE)
+        assert int(bs.code_lengths(r, 32, 4, isometries=True)[0]) == 1 + 2 + 8 + 3 * M + 4
+
+
+def level_bits(rec, b_max, b_min):
+    return int(np.sum(np.where(bs.level_elided(rec, b_max, b_min), 0, bs.LEVEL_BITS)))
+
+
+@pytest.mark.parametrize("W,H,bm,bmin,seed", [(96, 160, 32, 4, 1), (64, 48, 16, 4, 3), (112, 80, 8, 4, 4),
+                                              (288, 160, 16, 8, 8)])
+def test_technique2_level_bits(W, H, bm, bmin, seed):
+    r = random_stream(W, H, bm, bmin, seed)
+    L = mns.num_levels(bm, bmin)
+    last = int(np.sum(r["level"] == L - 1))
+    assert last % 4 == 0
+    assert level_bits(r, bm, bmin) == 2 * (r.size - last) + 2 * last // 4
+
+
+def test_technique2_matches_the_papers_figures():
+    # 4000 last-level blocks: 8000 identification bits before, 2000 with Technique 2
+    assert 2 * 4000 == 8000 and 2 * 4000 // 4 == 2000
+    # 25000 blocks: 6.25 KB before, about 1.5 KB after
+    assert 2 * 25000 / 8 / 1000 == 6.25
+    assert abs(2 * 25000 // 4 / 8 / 1000 - 1.5) < 0.07
+
+
+@pytest.mark.parametrize("name,make,b_max,b_min,thr,iso", [
+    ("c1", lambda: synth.workload("c1"), 8, 4, [600], True),
+    ("c2", lambda: synth.workload("c2"), 16, 4, [300, 200], True),
+    ("c2 identity", lambda: synth.workload("c2"), 16, 4, [300, 200], False),
+    ("pw 32", lambda: synth.piecewise_smooth(192, 256, 13, cells=40), 32, 4, [120, 90, 60], True),
+    ("noise 4", lambda: synth.noise_1f(16, 24, 18), 4, 4, [], True),
+])
+def test_round_trip_encoded(name, make, b_max, b_min, thr, iso):
+    img = make()
+    H, W = img.shape
+    r = mns.encode(img, b_max, b_min, thr, isometries=iso)
+    data, nbits = bs.pack(r, W, H, b_max, b_min, isometries=iso)
+    assert nbits == bs.HEADER_BITS + int(bs.code_lengths(r, b_max, b_min, iso).sum())
+    back, W2, H2, bm2, bmin2, iso2 = bs.unpack(data, nbits)
+    assert (W2, H2, bm2, bmin2, iso2) == (W, H, b_max, b_min, iso)
+    assert back.tobytes() == np.ascontiguousarray(r).tobytes()
+
+
+@pytest.mark.parametrize("W,H,bm,bmin,seed", [(96, 160, 32, 4, 1), (160, 96, 32, 8, 2), (64, 48, 16, 4, 3),
+                                              (64, 64, 4, 4, 5), (264, 136, 8, 4, 6)])
+def test_round_trip_random(W, H, bm, bmin, seed):
+    r = random_stream(W, H, bm, bmin, seed, bounded=True)
+    data, nbits = bs.pack(r, W, H, bm, bmin, isometries=True)
+    back = bs.unpack(data, nbits)[0]
+    assert back.tobytes() == r.tobytes()
+
+
+def test_identity_stream_needs_no_isometry_bits():
+    r = mns.encode(synth.workload("c1"), 8, 4, [600])
+    assert np.any(r["iso"] != 0)
+    with pytest.raises(ValueError):
+        bs.pack(r, 64, 64, 8, 4, isometries=False)
+    ri = mns.encode(synth.workload("c1"), 8, 4, [600], isometries=False)
+    assert np.all(ri["iso"] == 0)
+
+
+def test_truncated_stream_is_an_error():
+    recs, bits = tiny_mixed()
+    with pytest.raises(ValueError):
+        bs.unpack(to_bytes(bits), len(bits) - 3)
+
+
+def test_planted_mistakes_fail_the_spelled_out_streams(monkeypatch):
+    # no Technique 2
+    monkeypatch.setattr(bs, "level_elided", lambda rec, b_max, b_min: np.zeros(np.asarray(rec).size, bool))
+    with pytest.raises(AssertionError):
+        _check_tiny(tiny_mixed, 16, 16, 8, 4, False)
+    monkeypatch.undo()
+    # two's complement instead of sign and magnitude
+    monkeypatch.setattr(bs, "_sign_magnitude", lambda v, M: int(v) & ((1 << M) - 1))
+    with pytest.raises(AssertionError):
+        _check_tiny(tiny_mixed, 16, 16, 8, 4, False)
