@@ -296,6 +296,51 @@ fe_status fe_decode_set_mode(fe_ctx* ctx, int mode);
 int fe_decode_last(const fe_ctx* ctx);
 
 /*
+ * The compressed file (Sec. 3.3; Technique 2, Sec. 3.4).  A 64-bit header
+ * (W - 1 and H - 1 in 16 bits each, log2 b_max and log2 b_min in 3 bits
+ * each, the isometry flag in 1 bit, 25 zero bits) is followed by one code
+ * per transform in stream order.  Bits are numbered from the least
+ * significant bit of byte 0 upwards and every field is written least
+ * significant bit first.  A code is: the phase bit (1 = phase 2); the
+ * 0-based level in 2 bits, left out for a block of the last level that is
+ * not the top-left child of its parent (Technique 2); the luminance byte
+ * (m, or O_i in phase 2); then, in phase 1, the contrast k in 3 bits and,
+ * with FE_PACK_ISOMETRY, the isometry in 3 bits (14 or 17 bits in all); in
+ * phase 2, O_c - O_i for c = 0, 1, 2 as M-bit sign (1 = negative) and
+ * magnitude, M = 5 at level 1 and 6 below, then the 4 contrast bits (30 or
+ * 33 bits).  No domain position is stored: the decoder places each block at
+ * the next free cell of the depth-first walk and gives it its co-centred
+ * domain (Sec. 3).
+ *
+ * fe_pack writes the file of one image's stream (d_t, n transforms, as
+ * fe_encode returns it) to d_out (device, 8-byte aligned, cap bytes; the
+ * file takes ceil(bits / 64) * 8 bytes, zero-padded) and its exact length
+ * in bits to *n_bits.  The stream must be in encoder order with co-centred
+ * domains, and W, H multiples of b_max (FE_ERR_INVALID otherwise, as for
+ * fields a code cannot hold: phase-2 differences beyond +-(2^(M-1) - 1), or
+ * an isometry other than the identity without FE_PACK_ISOMETRY, which the
+ * encoder's FE_IDENTITY_ONLY guarantees).  FE_ERR_CAPACITY if cap is too
+ * small.  Waits for the stream.  fe_pack_bound gives a cap that always
+ * suffices for n transforms.
+ *
+ * fe_unpack (host only, no device) parses a file of n_bits bits back into
+ * transforms (h_out, cap; co-centred dx, dy filled in) and the header's
+ * fields (*info).  FE_ERR_INVALID for a malformed file (truncated, a level
+ * out of range, a block that does not fit the next free cell);
+ * FE_ERR_CAPACITY if cap is too small, with *n_out set to the number needed.
+ */
+#define FE_PACK_ISOMETRY 1u
+typedef struct fe_stream_info {
+  uint32_t width, height, b_max, b_min, flags;
+} fe_stream_info;
+size_t fe_pack_bound(size_t n);
+fe_status fe_pack(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t width, uint32_t height,
+                  uint32_t b_max, uint32_t b_min, uint32_t flags, uint8_t* d_out, size_t cap,
+                  uint64_t* n_bits, void* stream);
+fe_status fe_unpack(const uint8_t* h_bits, uint64_t n_bits, fe_transform* h_out, size_t cap, size_t* n_out,
+                    fe_stream_info* info);
+
+/*
  * Exhaustive search of explicit ranges (Sec. 1): for each range of side
  * `block` (4, 8 or 16) at d_xy[i] (x | y << 16, multiples of block), find
  * the best of all (W - 2B + 1)(H - 2B + 1) step-1 domains, 8 isometries and

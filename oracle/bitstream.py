@@ -137,6 +137,8 @@ def pack(rec: np.ndarray, width: int, height: int, b_max: int, b_min: int,
             elif int(r["iso"]) != 0:
                 raise ValueError("an isometry other than the identity needs the isometry flag")
         else:
+            if lvl >= L - 1:
+                raise ValueError("phase 2 stands for a range above the last level")
             M = PHASE2_BITS[lvl + 1]
             for c in range(3):
                 w.put(_sign_magnitude(int(r["dlum"][c]), M), M)
@@ -196,6 +198,8 @@ def unpack(data: bytes, nbits: int | None = None):
             r["s_idx"] = rd.get(3)
             r["iso"] = rd.get(3) if isometries else 0
         else:
+            if lvl >= L - 1:
+                raise ValueError("phase 2 at the last level")
             r["flags"] = FLAG_PHASE2
             M = PHASE2_BITS[lvl + 1]
             d = []

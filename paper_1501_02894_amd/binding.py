@@ -46,6 +46,11 @@ class fe_params(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("mse_thr", ctypes.c_uint32 * 4)]
 
 
+class fe_stream_info(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("b_max", ctypes.c_uint32),
+                ("b_min", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
 class fe_image_desc(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
                 ("stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
@@ -78,6 +83,10 @@ _SIGNATURES = {
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
     "fe_decode_set_mode": (ctypes.c_int, [_VP, ctypes.c_int]),
     "fe_decode_last": (ctypes.c_int, [_VP]),
+    "fe_pack_bound": (_SZ, [_SZ]),
+    "fe_pack": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _U32, _VP, _SZ, ctypes.POINTER(ctypes.c_uint64),
+                               _VP]),
+    "fe_unpack": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _SZ, ctypes.POINTER(_SZ), ctypes.POINTER(fe_stream_info)]),
     "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
                                         ctypes.POINTER(_VP)]),
@@ -305,6 +314,44 @@ def fe_decode_set_mode(ctx: int, mode: int) -> None:
 
 def fe_decode_last(ctx: int) -> int:
     return int(load().fe_decode_last(ctx))
+
+
+FE_PACK_ISOMETRY = 1
+
+
+def fe_pack_bound(n: int) -> int:
+    return int(load().fe_pack_bound(n))
+
+
+def fe_pack(ctx: int, transforms, width: int, height: int, b_max: int, b_min: int, isometry: bool = True,
+            out=None, stream=None):
+    """Compressed file of one image's transform stream (device (n, 16)
+    uint8); returns (device uint8 buffer, length in bits)."""
+    import torch
+    n = int(transforms.shape[0])
+    if out is None:
+        out = torch.empty(fe_pack_bound(n), dtype=torch.uint8, device=transforms.device)
+    nb = ctypes.c_uint64(0)
+    _check(load().fe_pack(ctx, _ptr(transforms), n, width, height, b_max, b_min,
+                          FE_PACK_ISOMETRY if isometry else 0, _ptr(out), int(out.numel()), ctypes.byref(nb),
+                          _stream(stream)))
+    return out, int(nb.value)
+
+
+def fe_unpack(data, n_bits: int):
+    """Parse a compressed file (host bytes) -> (records, info dict)."""
+    buf = np.frombuffer(bytes(data), dtype=np.uint8)
+    info = fe_stream_info()
+    n = _SZ(0)
+    lib = load()
+    st = lib.fe_unpack(buf.ctypes.data, n_bits, None, 0, ctypes.byref(n), ctypes.byref(info))
+    if st not in (FE_OK, FE_ERR_CAPACITY):
+        _check(st)
+    out = np.zeros(n.value, TRANSFORM_DTYPE)
+    _check(lib.fe_unpack(buf.ctypes.data, n_bits, out.ctypes.data if n.value else None, n.value, ctypes.byref(n),
+                         ctypes.byref(info)))
+    return out, {"width": info.width, "height": info.height, "b_max": info.b_max, "b_min": info.b_min,
+                 "isometry": bool(info.flags & FE_PACK_ISOMETRY)}
 
 
 def fe_full_search_ranges(ctx: int, img, block: int, xy, out=None, stream=None):

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["mns_encode.hip", "order.hip", "mns_steps.hip", "decode.hip", "fullsearch.hip", "server.cpp",
+HIP_SOURCES = ["mns_encode.hip", "order.hip", "mns_steps.hip", "decode.hip", "fullsearch.hip", "bitstream.hip",
+               "bitstream_host.cpp", "server.cpp",
                "fe_host.cpp", "fe_common.cpp"]
 
 # Packed-FP32 instructions are kept out of every kernel; the host pass does

@@ -64,6 +64,8 @@ struct fe_ctx {
   size_t dec_cells_n = 0;
   uint2* dec_pieces = nullptr;        // decoder plan: pieces per block
   size_t dec_pieces_n = 0;
+  uint64_t* pack_chunk = nullptr;     // bitstream: chunk sums, then chunk bases
+  size_t pack_chunk_n = 0;
   bool last_decode_tiled = false;     // which decoder the last fe_decode ran
   int decode_mode = FE_DECODE_AUTO;
   fe::TileShape shape_override[33][5] = {};
@@ -505,6 +507,7 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->dec_tiles);
   (void)hipFree(c->dec_cells);
   (void)hipFree(c->dec_pieces);
+  (void)hipFree(c->pack_chunk);
   if (c->ev) {
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
       if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -618,6 +621,54 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
     else
       FE_HIP(fe::launch_decode_iter(a, cur, nxt, s), "decode launch");
   }
+  return FE_OK;
+}
+
+size_t fe_pack_bound(size_t n) { return 8 + ((33 * (uint64_t)n + 63) / 64) * 8; }
+
+fe_status fe_pack(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
+                  uint32_t b_min, uint32_t flags, uint8_t* d_out, size_t cap, uint64_t* n_bits, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_out || !n_bits || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (((uintptr_t)d_out & 7) || ((uintptr_t)d_t & 15)) return fe::fail(FE_ERR_INVALID, "misaligned buffer");
+  if (flags & ~FE_PACK_ISOMETRY) return fe::fail(FE_ERR_INVALID, "unknown pack flags 0x%x", flags);
+  if (!fe::is_pow2(b_max) || !fe::is_pow2(b_min) || b_min < 4 || b_max > 32 || b_min > b_max)
+    return fe::fail(FE_ERR_INVALID, "bad block sizes %u, %u", b_max, b_min);
+  if (w % b_max || h % b_max || w < 2 * b_max || h < 2 * b_max || w > 65536 || h > 65536)
+    return fe::fail(FE_ERR_SHAPE, "image %ux%u does not tile with b_max %u", w, h, b_max);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int L = fe::levels_of(b_max, b_min);
+  const size_t ntiles = (size_t)(w / b_max) * (h / b_max);
+  const size_t chunks = std::max<size_t>(fe::pack_chunks(n), 1);
+  fe_status st = ensure(ctx->dec_tiles, ctx->dec_tiles_n, ntiles + 1, "tile starts");
+  if (st == FE_OK) st = ensure(ctx->pack_chunk, ctx->pack_chunk_n, 2 * chunks, "pack chunk sums");
+  if (st != FE_OK) return st;
+  // the stream's structure (encoder order, co-centred domains) and fields
+  fe::DecodeArgs a{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
+  FE_HIP(fe::launch_zero_u32(ctx->flags, 4, s), "zero flags");
+  if (n) {
+    FE_HIP(fe::launch_decode_check(a, ctx->flags, s), "check launch");
+    FE_HIP(fe::launch_decode_tile_setup(a, ctx->dec_tiles, ctx->flags + 1, s), "order check");
+  }
+  const uint64_t header = (uint64_t)(w - 1) | ((uint64_t)(h - 1) << 16) |
+                          ((uint64_t)(31 - __builtin_clz(b_max)) << 32) | ((uint64_t)(31 - __builtin_clz(b_min)) << 35) |
+                          ((uint64_t)((flags & FE_PACK_ISOMETRY) ? 1 : 0) << 38);
+  uint64_t* total = reinterpret_cast<uint64_t*>(ctx->flags + 2);
+  FE_HIP(fe::launch_pack(reinterpret_cast<const uint4*>(d_t), (uint64_t)n, L, (int)b_min,
+                         (flags & FE_PACK_ISOMETRY) != 0, header, ctx->pack_chunk, ctx->pack_chunk + chunks, total,
+                         ctx->flags, reinterpret_cast<unsigned long long*>(d_out), (uint64_t)(cap / 8), s),
+         "pack launch");
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "pack read-back");
+  FE_HIP(hipStreamSynchronize(s), "pack");
+  const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
+  const uint32_t disorder = (uint32_t)(ctx->h_scalars[0] >> 32);
+  const uint64_t bits = ctx->h_scalars[1];
+  if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms have fields their codes cannot hold", bad);
+  if (disorder) return fe::fail(FE_ERR_INVALID, "the stream is not in encoder order with co-centred domains");
+  *n_bits = bits;
+  const uint64_t need = (bits + 63) / 64 * 8;
+  if (need > cap) return fe::fail(FE_ERR_CAPACITY, "the file needs %llu bytes, cap is %zu", (unsigned long long)need, cap);
   return FE_OK;
 }
 

@@ -114,6 +114,15 @@ hipError_t launch_decode_plan(const DecodeArgs& a, const uint32_t* tile_start, u
 hipError_t launch_decode_tile_iter(const DecodeArgs& a, const uint8_t* cells, const uint2* pieces,
                                    const uint8_t* cur, uint8_t* nxt, hipStream_t stream);
 
+// Bitstream packing (Sec. 3.3, 3.4): chunk_bits / chunk_base hold
+// pack_chunks(n) words (at least one), *total receives the stream length in
+// bits (header included), *bad the number of transforms whose fields do not
+// fit their codes; out holds cap_words 64-bit words.
+size_t pack_chunks(uint64_t n);
+hipError_t launch_pack(const uint4* t, uint64_t n, int L, int b_min, bool iso, uint64_t header_word,
+                       uint64_t* chunk_bits, uint64_t* chunk_base, uint64_t* total, uint32_t* bad,
+                       unsigned long long* out, uint64_t cap_words, hipStream_t stream);
+
 // Exhaustive search (one image).  Plans, the 2x2 phase planes, per-level
 // domain sums, the MFMA search of a list of ranges (best key per range),
 // and the per-range finalisation into records / next-level ranges.

@@ -26,7 +26,9 @@ def random_stream(width: int, height: int, b_max: int, b_min: int, seed: int,
     def leaf(x, y, B, level):
         r = np.zeros((), mns.RECORD_DTYPE)
         r["x"], r["y"], r["level"] = x, y, level
-        if B >= 8 and level <= 2 and rng.random() < p_phase2:
+        # phase 2 stands for a range that phase 1 did not accept, so an
+        # encoder never emits it at the last level (a decoder still can take it)
+        if B >= 8 and level <= 2 and (B > b_min or not bounded) and rng.random() < p_phase2:
             m = int(rng.integers(40, 216))
             if bounded:
                 delta = mns.PHASE2_DELTA[level + 1]
