@@ -205,6 +205,40 @@ def bench_fullsearch(fb, ctx, img, b_max, b_min, thr, reps=2):
             "mfma_frac": 2 * macs / (search_ms / 1e3) / 5.0e15}
 
 
+def bench_bitstream(fb, ctx, img, b_max, b_min, thr, reps=5):
+    """The compressed file of Sec. 3.3 (Technique 2 of Sec. 3.4) for one
+    image, with the 8-isometry codes and with the paper's identity-only
+    14-bit codes: size (bits per pixel, compression ratio), the PSNR of 12
+    decoder iterations from grey, and the time to pack (GPU, call wall
+    time) and to parse (native, host)."""
+    import torch
+    H, W = img.shape
+    t = torch.from_numpy(img).cuda()
+    res = {}
+    for iso in (True, False):
+        recs = fb.fe_encode(ctx.handle, t, fb.make_params(b_max, b_min, thr, identity_only=not iso))
+        out = torch.empty(fb.fe_pack_bound(int(recs.shape[0])), dtype=torch.uint8, device="cuda")
+        fb.fe_pack(ctx.handle, recs, W, H, b_max, b_min, isometry=iso, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, nbits = fb.fe_pack(ctx.handle, recs, W, H, b_max, b_min, isometry=iso, out=out)
+        pack_ms = (time.perf_counter() - t0) * 1e3 / reps
+        data = out[: (nbits + 7) // 8].cpu().numpy().tobytes()
+        t0 = time.perf_counter()
+        back, _ = fb.fe_unpack(data, nbits)
+        unpack_ms = (time.perf_counter() - t0) * 1e3
+        same = back.tobytes() == fb.to_records(recs).tobytes()
+        dec = fb.fe_decode(ctx.handle, recs, W, H, b_max, 12).cpu().numpy().astype(np.float64)
+        mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
+        psnr = 10.0 * np.log10(255.0 ** 2 / mse) if mse > 0 else float("inf")
+        res["isometries" if iso else "identity_only"] = {
+            "transforms": int(recs.shape[0]), "bits": nbits, "bpp": nbits / (W * H),
+            "compression_ratio": 8.0 * W * H / (8 * ((nbits + 7) // 8)), "psnr_db_12_iters": psnr,
+            "pack_call_ms": pack_ms, "unpack_ms": unpack_ms, "parsed_equal": same}
+    return res
+
+
 def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     """Poisson arrivals at `rate`; returns served images/s and latency
     percentiles (scheduled arrival -> records in host memory).  `pool` holds
@@ -548,6 +582,8 @@ def main():
         result["c3_single"] = res_c3
         result["c3_decode"] = res_dec
         result["c2_fullsearch"] = res_fs
+        result["bitstream"] = {"c2": bench_bitstream(fb, ctx, c2, 16, 4, [300, 200]),
+                               "c3": bench_bitstream(fb, ctx, c3, 32, 4, [150, 100, 64])}
         print(f"[bench] single/decode/full-search done", file=sys.stderr, flush=True)
 
     if not args.no_serving:
