@@ -239,6 +239,35 @@ def bench_bitstream(fb, ctx, img, b_max, b_min, thr, reps=5):
     return res
 
 
+def bench_tradeoff(fb, ctx, images, b_max=16, b_min=4, reps=5):
+    """No-search (phase 1 only) against MNS (Technique 1 on) over a sweep of
+    thresholds, with the paper's codes (identity only, 14-bit phase 1): per
+    point the file size (bpp), the PSNR after 12 decoder iterations from
+    grey, and the encode time (fused kernel, HIP events; call wall time)."""
+    import torch
+    pts = []
+    # t2 from 100 to about 900 in steps of 1.15, t1 = 1.5 t2 (the transition
+    # from 4 x 4 blocks to whole tiles lies in this range on these images)
+    sweep = [(int(round(1.5 * 100 * 1.15 ** k)), int(round(100 * 1.15 ** k))) for k in range(16)]
+    for name, img in images.items():
+        H, W = img.shape
+        t = torch.from_numpy(img).cuda()
+        for phase2 in (False, True):
+            for thr in sweep:
+                p = fb.make_params(b_max, b_min, thr, phase2=phase2, identity_only=True)
+                recs = fb.fe_encode(ctx.handle, t, p)
+                kms, _, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE, lambda: fb.fe_encode(ctx.handle, t, p), reps)
+                _, nbits = fb.fe_pack(ctx.handle, recs, W, H, b_max, b_min, isometry=False)
+                dec = fb.fe_decode(ctx.handle, recs, W, H, b_max, 12).cpu().numpy().astype(np.float64)
+                mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
+                pts.append({"image": name, "method": "mns" if phase2 else "no-search", "thresholds": list(thr),
+                            "transforms": int(recs.shape[0]),
+                            "phase2_transforms": int((recs[:, 9] != 0).sum().item()), "bits": nbits,
+                            "bpp": nbits / (W * H), "psnr_db": 10.0 * np.log10(255.0 ** 2 / mse),
+                            "kernel_ms": kms, "call_ms": wall})
+    return pts
+
+
 def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     """Poisson arrivals at `rate`; returns served images/s and latency
     percentiles (scheduled arrival -> records in host memory).  `pool` holds
@@ -362,6 +391,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--decode-only", action="store_true",
                     help="only decode C3 (4096^2, 32 -> 4) with both decoders (a profiling workload)")
+    ap.add_argument("--tradeoff", action="store_true",
+                    help="only the no-search vs MNS sweep (bpp, PSNR, time) on two 512^2 images")
     ap.add_argument("--fullsearch-only", action="store_true",
                     help="only the exhaustive-search encode of C2 (512^2, 16 -> 4) (a profiling workload)")
     args = ap.parse_args()
@@ -376,6 +407,16 @@ def main():
     dev = torch.device("cuda:0")
     if args.decode_only:
         decode_only(fb, args)
+        return
+    if args.tradeoff:
+        from paper_1501_02894_amd import synth
+        ctx = fb.Context(0)
+        imgs = {"c2 (1/f noise + polygons)": synth.workload("c2"),
+                "rough 1/f noise (beta 1.5)": synth.noise_1f(512, 512, 22, beta=1.5)}
+        pts = bench_tradeoff(fb, ctx, imgs)
+        ctx.close()
+        print(json.dumps({"workload": "no-search vs MNS, 512^2, 16 -> 4, identity-only codes", "points": pts}),
+              flush=True)
         return
     if args.fullsearch_only:
         from paper_1501_02894_amd import synth
