@@ -118,14 +118,17 @@ typedef struct fe_transform {
 #define FE_FULL_SEARCH 2u  /* exhaustive step-1 search (Sec. 1) instead of the co-centred domain; no phase 2 */
 #define FE_IDENTITY_ONLY 4u /* phase 1 fits the identity isometry only: the stream then fits the paper's
                               14-bit phase-1 code (Sec. 3.3), which stores no isometry; MNS only */
+#define FE_LOCAL_SEARCH 8u  /* local search (Sec. 2): the best of the 2B x 2B blocks that contain the range
+                              (step 1, (B+1)^2 away from the borders), identity only; no phase 2;
+                              same limits as FE_FULL_SEARCH */
 
 /*
  * Encoder parameters.
  *   b_max, b_min  largest and smallest range side: powers of two with
  *                 4 <= b_min <= b_max <= 32 (at most four levels, Sec. 3.3).
  *   n_thr         number of thresholds = L - 1, L = log2(b_max/b_min) + 1.
- *   flags         FE_PHASE2, FE_FULL_SEARCH, FE_IDENTITY_ONLY (not with
- *                 FE_FULL_SEARCH).
+ *   flags         FE_PHASE2, FE_FULL_SEARCH, FE_IDENTITY_ONLY (MNS only),
+ *                 FE_LOCAL_SEARCH (not with FE_FULL_SEARCH).
  *   mse_thr[l-1]  integer MSE threshold t_l of level l = 1..L-1 (the last
  *                 level is always stored, Sec. 3); unused entries ignored.
  */

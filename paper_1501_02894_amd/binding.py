@@ -20,6 +20,7 @@ FE_OK, FE_ERR_INVALID, FE_ERR_SHAPE, FE_ERR_CAPACITY, FE_ERR_DEVICE, FE_ERR_OOM,
 FE_PHASE2 = 1
 FE_FULL_SEARCH = 2
 FE_IDENTITY_ONLY = 4
+FE_LOCAL_SEARCH = 8
 FE_TRANSFORM_PHASE2 = 1
 
 # 16-byte transform layout of include/fe.h (little-endian).
@@ -158,13 +159,13 @@ def _stream(stream=None) -> int:
 
 
 def make_params(b_max: int, b_min: int, thresholds, phase2: bool = True, full_search: bool = False,
-                identity_only: bool = False) -> fe_params:
+                identity_only: bool = False, local_search: bool = False) -> fe_params:
     p = fe_params()
     p.b_max, p.b_min = int(b_max), int(b_min)
     thr = [int(t) for t in thresholds]
     p.n_thr = len(thr)
     p.flags = ((FE_PHASE2 if phase2 else 0) | (FE_FULL_SEARCH if full_search else 0) |
-               (FE_IDENTITY_ONLY if identity_only else 0))
+               (FE_IDENTITY_ONLY if identity_only else 0) | (FE_LOCAL_SEARCH if local_search else 0))
     for i, t in enumerate(thr[:4]):
         p.mse_thr[i] = t
     return p
@@ -557,9 +558,10 @@ class Context:
     def range_moments(self, img, block, xy, **kw):
         return fe_range_moments(self.handle, img, block, xy, **kw)
 
-    def encode(self, img, b_max, b_min, thresholds, phase2=True, full_search=False, identity_only=False, **kw):
-        return fe_encode(self.handle, img, make_params(b_max, b_min, thresholds, phase2, full_search, identity_only),
-                         **kw)
+    def encode(self, img, b_max, b_min, thresholds, phase2=True, full_search=False, identity_only=False,
+               local_search=False, **kw):
+        return fe_encode(self.handle, img, make_params(b_max, b_min, thresholds, phase2, full_search, identity_only,
+                                                       local_search), **kw)
 
     def encode_batch(self, imgs, b_max, b_min, thresholds, phase2=True, **kw):
         return fe_encode_batch(self.handle, imgs, make_params(b_max, b_min, thresholds, phase2), **kw)

@@ -41,10 +41,12 @@ fe_status check_params(const fe_params* p) {
   const int L = levels_of(p->b_max, p->b_min);
   if (p->n_thr != (uint32_t)(L - 1))
     return fail(FE_ERR_INVALID, "n_thr must be %d (one per level except the last), got %u", L - 1, p->n_thr);
-  if (p->flags & ~(FE_PHASE2 | FE_FULL_SEARCH | FE_IDENTITY_ONLY))
+  if (p->flags & ~(FE_PHASE2 | FE_FULL_SEARCH | FE_IDENTITY_ONLY | FE_LOCAL_SEARCH))
     return fail(FE_ERR_INVALID, "unknown flags 0x%x", p->flags);
-  if ((p->flags & FE_FULL_SEARCH) && (p->flags & FE_IDENTITY_ONLY))
+  if ((p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) && (p->flags & FE_IDENTITY_ONLY))
     return fail(FE_ERR_INVALID, "FE_IDENTITY_ONLY applies to the co-centred (MNS) search only");
+  if ((p->flags & FE_FULL_SEARCH) && (p->flags & FE_LOCAL_SEARCH))
+    return fail(FE_ERR_INVALID, "FE_FULL_SEARCH and FE_LOCAL_SEARCH exclude each other");
   return FE_OK;
 }
 

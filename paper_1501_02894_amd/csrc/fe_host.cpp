@@ -233,7 +233,7 @@ fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_par
   if (!h_imgs || !d_out || !d_offsets || n_imgs == 0) return fe::fail(FE_ERR_INVALID, "NULL argument");
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
-  if (p->flags & FE_FULL_SEARCH) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
+  if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
   for (uint32_t k = 0; k < n_imgs; ++k) {
     if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
@@ -419,9 +419,13 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
     FE_HIP(fe::fs_domain_sums(pl, w, h, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, s), "domain sums");
     {
       Timed t(ctx, FE_TIMING_FULLSEARCH, s);
-      FE_HIP(fe::fs_search(pl, d_img, w, h, stride, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, xy, R, ctx->fs_frag,
-                           ctx->fs_sr, ctx->fs_alpha, ctx->fs_beta, ctx->fs_best, s),
-             "search launch");
+      if (p->flags & FE_LOCAL_SEARCH)
+        FE_HIP(fe::ls_search(pl, d_img, w, h, stride, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, xy, R, ctx->fs_best, s),
+               "local search launch");
+      else
+        FE_HIP(fe::fs_search(pl, d_img, w, h, stride, ctx->fs_planes, ctx->fs_sd, ctx->fs_qd, xy, R, ctx->fs_frag,
+                             ctx->fs_sr, ctx->fs_alpha, ctx->fs_beta, ctx->fs_best, s),
+               "search launch");
     }
     FE_HIP(fe::launch_zero_u32(ctx->flags, 1, s), "zero count");
     const bool last = lev == L;
@@ -552,7 +556,8 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, u
   if ((uintptr_t)d_img & 3) return fe::fail(FE_ERR_SHAPE, "image must be 4-byte aligned");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
   DeviceGuard g(ctx->device);
-  if (p->flags & FE_FULL_SEARCH) return encode_full_search(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
+  if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH))
+    return encode_full_search(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
   fe_image_desc one{d_img, w, h, stride, 0};
   return encode_images(ctx, &one, 1, p, d_out, cap, nullptr, n_out, (hipStream_t)stream);
 }

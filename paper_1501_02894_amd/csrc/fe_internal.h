@@ -138,6 +138,11 @@ FsPlan fs_plan(uint32_t w, uint32_t h, uint32_t B);
 size_t fs_frag_bytes(uint32_t B, uint32_t R);
 hipError_t fs_planes(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
                      uint8_t* planes, hipStream_t s);
+// Local search (Sec. 2): best surrounding step-1 domain of each listed range
+// (identity only), as a best key for fs_finalize.
+hipError_t ls_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                     const uint8_t* planes, const uint32_t* sd, const double* qd, const uint32_t* xy, uint32_t R,
+                     uint64_t* best, hipStream_t stream);
 hipError_t fs_domain_sums(const FsPlan& pl, uint32_t w, uint32_t h, const uint8_t* planes, uint32_t* sd,
                           double* qd, hipStream_t s);
 hipError_t fs_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,

@@ -357,6 +357,75 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
   }
 }
 
+// ------------------------------------------------------------------ local search
+// Local search (Sec. 2): the candidates of a B x B range at (x, y) are the
+// 2B x 2B blocks that contain it, step-1 origins x - B <= u <= x and
+// y - B <= v <= y inside the image ((B+1)^2 away from the borders), with the
+// identity only.  One wave per range: every lane holds the range's rows in
+// registers, scores candidates lane, lane + 64, ... exactly in integers
+// (Sum r d from the phase planes, Sum d and Q of the domain from the domain
+// sums), and the wave keeps the least key, so that the finalisation of the
+// exhaustive search applies unchanged.
+template <int B>
+__global__ __launch_bounds__(256) void ls_search_kernel(FsGeo g, const uint8_t* __restrict__ img, uint32_t stride,
+                                                       const uint32_t* __restrict__ sd, const double* __restrict__ qd,
+                                                       const uint32_t* __restrict__ xy, uint32_t R,
+                                                       uint64_t* __restrict__ best) {
+  constexpr int Q4 = B / 4;
+  constexpr int64_t N = B * B;
+  const int lane = threadIdx.x & 63;
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;   // the whole wave: nothing below synchronises the workgroup
+  const int x = (int)(xy[r] & 0xffffu), y = (int)(xy[r] >> 16);
+  uint32_t rr[B][Q4];
+  uint32_t srs = 0;
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int q = 0; q < Q4; ++q) {
+      rr[i][q] = *reinterpret_cast<const uint32_t*>(img + (size_t)(y + i) * stride + x + 4 * q);
+      srs = __builtin_amdgcn_udot4(rr[i][q], 0x01010101u, srs, false);
+    }
+  const int64_t sr = (int64_t)srs;
+  const int u0 = max(0, x - B), u1 = min(x, (int)g.w - 2 * B);
+  const int v0 = max(0, y - B), v1 = min(y, (int)g.h - 2 * B);
+  const int cu = u1 - u0 + 1, nc = cu * (v1 - v0 + 1);
+  uint64_t key = ~0ull;
+  for (int c = lane; c < nc; c += 64) {
+    const int v = v0 + c / cu, u = u0 + c % cu;
+    const uint32_t dom = (uint32_t)v * g.nu + (uint32_t)u;
+    const uint8_t* o = domain_origin_ptr(g, (uint32_t)u, (uint32_t)v);
+    const uint32_t sh = (uint32_t)((uintptr_t)o & 3u);
+    const uint32_t* a = reinterpret_cast<const uint32_t*>((uintptr_t)o & ~(uintptr_t)3);
+    const uint32_t pw = g.pitch / 4;
+    uint32_t srd = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      uint32_t w[Q4 + 1];
+#pragma unroll
+      for (int q = 0; q <= Q4; ++q) w[q] = a[(size_t)i * pw + q];
+#pragma unroll
+      for (int q = 0; q < Q4; ++q)
+        srd = __builtin_amdgcn_udot4(rr[i][q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], sh), srd, false);
+    }
+    const int64_t d = (int64_t)sd[dom];
+    const int64_t Q = (int64_t)qd[dom];
+    const int64_t P = N * (int64_t)srd - sr * d;
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) k += ((int64_t)(2 * j + 1) * Q < 16 * P) ? 1 : 0;
+    const int64_t f = (int64_t)(k * k) * Q - (int64_t)(16 * k) * P;
+    const uint64_t kk = cand_key(f, dom, 0);
+    key = kk < key ? kk : key;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o2 = __shfl_xor(key, off);
+    key = o2 < key ? o2 : key;
+  }
+  if (lane == 0) best[r] = key;
+}
+
 // ------------------------------------------------------------------ finalize
 // Per range: decode the best key, recompute Sum r T_e(D) exactly, derive k,
 // m and S, store the record (accepted, or forced at the last level) or
@@ -551,6 +620,21 @@ hipError_t fs_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t 
     case 4: return fs_search_t<4, 4>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t ls_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,
+                     const uint8_t* planes, const uint32_t* sd, const double* qd, const uint32_t* xy, uint32_t R,
+                     uint64_t* best, hipStream_t s) {
+  if (R == 0) return hipSuccess;
+  const FsGeo g = geo_of(pl, w, h, planes);
+  const dim3 grid((R + 3) / 4);
+  switch (pl.B) {
+    case 16: hipLaunchKernelGGL(ls_search_kernel<16>, grid, dim3(256), 0, s, g, img, stride, sd, qd, xy, R, best); break;
+    case 8: hipLaunchKernelGGL(ls_search_kernel<8>, grid, dim3(256), 0, s, g, img, stride, sd, qd, xy, R, best); break;
+    case 4: hipLaunchKernelGGL(ls_search_kernel<4>, grid, dim3(256), 0, s, g, img, stride, sd, qd, xy, R, best); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t fs_finalize(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t h, uint32_t stride,

@@ -70,8 +70,12 @@ def test_validation_codes():
     bad = fb.make_params(16, 4, [300])
     assert fb.fe_validate(64, 64, 64, bad) == fb.FE_ERR_INVALID
     bad = fb.make_params(16, 4, [300, 200])
-    bad.flags = 8
+    bad.flags = 16                                                # unknown flag
     assert fb.fe_validate(64, 64, 64, bad) == fb.FE_ERR_INVALID
+    for flags in (fb.FE_FULL_SEARCH | fb.FE_LOCAL_SEARCH, fb.FE_FULL_SEARCH | fb.FE_IDENTITY_ONLY,
+                  fb.FE_LOCAL_SEARCH | fb.FE_IDENTITY_ONLY):
+        bad.flags = flags                                         # combinations that exclude each other
+        assert fb.fe_validate(64, 64, 64, bad) == fb.FE_ERR_INVALID
     assert fb.load().fe_validate(64, 64, 64, None) == fb.FE_ERR_INVALID
 
 
