@@ -205,6 +205,27 @@ def bench_fullsearch(fb, ctx, img, b_max, b_min, thr, reps=2):
             "mfma_frac": 2 * macs / (search_ms / 1e3) / 5.0e15}
 
 
+def bench_localsearch(fb, ctx, img, b_max, b_min, thr, reps=3):
+    """Local search (Sec. 2) against MNS with the identity only, same image
+    and thresholds: search-kernel time, call time, transforms and the PSNR
+    after 12 decoder iterations from grey."""
+    import torch
+    H, W = img.shape
+    t = torch.from_numpy(img).cuda()
+    res = {}
+    for name, p, slot in (("local_search", fb.make_params(b_max, b_min, thr, local_search=True),
+                           fb.FE_TIMING_FULLSEARCH),
+                          ("mns_identity", fb.make_params(b_max, b_min, thr, identity_only=True),
+                           fb.FE_TIMING_ENCODE)):
+        recs = fb.fe_encode(ctx.handle, t, p)
+        kms, launches, wall = timed_kernel(fb, ctx, slot, lambda: fb.fe_encode(ctx.handle, t, p), reps)
+        dec = fb.fe_decode(ctx.handle, recs, W, H, b_max, 12).cpu().numpy().astype(np.float64)
+        mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
+        res[name] = {"transforms": int(recs.shape[0]), "kernel_ms_per_call": kms * launches, "call_ms": wall,
+                     "psnr_db_12_iters": 10.0 * np.log10(255.0 ** 2 / mse)}
+    return res
+
+
 def bench_bitstream(fb, ctx, img, b_max, b_min, thr, reps=5):
     """The compressed file of Sec. 3.3 (Technique 2 of Sec. 3.4) for one
     image, with the 8-isometry codes and with the paper's identity-only
@@ -623,6 +644,7 @@ def main():
         result["c3_single"] = res_c3
         result["c3_decode"] = res_dec
         result["c2_fullsearch"] = res_fs
+        result["c2_localsearch"] = bench_localsearch(fb, ctx, c2, 16, 4, [300, 200])
         result["bitstream"] = {"c2": bench_bitstream(fb, ctx, c2, 16, 4, [300, 200]),
                                "c3": bench_bitstream(fb, ctx, c3, 32, 4, [150, 100, 64])}
         print(f"[bench] single/decode/full-search done", file=sys.stderr, flush=True)
