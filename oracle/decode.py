@@ -141,6 +141,19 @@ def decode(rec: np.ndarray, width: int, height: int, b_max: int, iters: int,
     return x.astype(np.uint8)
 
 
+def zoom(rec: np.ndarray, factor: int) -> np.ndarray:
+    """Resolution-independent decoding (Sec. 1): the same maps at `factor`
+    times the size.  Ranges and domain origins scale by the factor, while
+    levels, contrasts and luminances stay; decode the result as a
+    (factor W) x (factor H) image with factor * b_max.  The co-centred
+    domain of a phase-2 sub-block scales the same way:
+    clamp(f x - f b / 2, 0, f W - 2 f b) = f clamp(x - b / 2, 0, W - 2 b)."""
+    out = np.array(rec, copy=True)
+    for k in ("x", "y", "dx", "dy"):
+        out[k] = out[k].astype(np.int64) * int(factor)
+    return out
+
+
 def fixed_point(rec: np.ndarray, width: int, height: int, b_max: int) -> np.ndarray:
     """Attractor of the unrounded map x = A x + b, by a direct sparse solve of
     (I - A) x = b (small images only)."""

@@ -137,15 +137,19 @@ def num_levels(b_max: int, b_min: int) -> int:
 def validate(width: int, height: int, b_max: int, b_min: int, thresholds) -> int:
     """Check the parameters; return the number of levels L.
 
-    B_max and B_min are powers of two with 4 <= B_min <= B_max <= 32 (four
-    quadtree levels at most, Sec. 3.3); W and H are multiples of B_max and at
-    least 2 B_max so that every co-centred 2B x 2B domain fits in the image;
-    one threshold per level except the last, which is always stored (Sec. 3).
+    B_max and B_min are powers of two with 2 <= B_min <= B_max and
+    4 <= B_max <= 32, and the quadtree has four levels at most (Sec. 3.3:
+    two bits of level number; the paper's own tree runs 16 x 16 down to
+    2 x 2); W and H are multiples of B_max and at least 2 B_max so that every
+    co-centred 2B x 2B domain fits in the image; one threshold per level
+    except the last, which is always stored (Sec. 3).
     """
     if not (_is_pow2(b_max) and _is_pow2(b_min)):
         raise ValueError("block sizes must be powers of two")
-    if not (4 <= b_min <= b_max <= 32):
-        raise ValueError("need 4 <= b_min <= b_max <= 32")
+    if not (2 <= b_min <= b_max and 4 <= b_max <= 32):
+        raise ValueError("need 2 <= b_min <= b_max, 4 <= b_max <= 32")
+    if num_levels(b_max, b_min) > 4:
+        raise ValueError("at most four quadtree levels (two level bits)")
     if width % b_max or height % b_max:
         raise ValueError("image sides must be multiples of b_max")
     if width < 2 * b_max or height < 2 * b_max:
@@ -179,6 +183,21 @@ def downsample(img: np.ndarray) -> np.ndarray:
     return (a + b + c + d + 2) // 4
 
 
+def phase_means(img: np.ndarray) -> np.ndarray:
+    """The 2 x 2 round-half-up mean images at the four pixel phases:
+    out[q, p, j, i] = mean of I[2j+q..2j+q+1][2i+p..2i+p+1] (zero where the
+    group would leave the image); out[0, 0] is H0.  A 2 x 2 range at x has
+    its domain at the odd origin x - 1, whose means lie on phase 1."""
+    I = np.asarray(img).astype(np.int64)
+    H, W = I.shape
+    out = np.zeros((2, 2, H // 2, W // 2), np.int64)
+    for q in range(2):
+        for p in range(2):
+            h, w = (H - q) // 2, (W - p) // 2
+            out[q, p, :h, :w] = downsample(I[q:q + 2 * h, p:p + 2 * w])
+    return out
+
+
 def domain_origin(p, B: int, extent: int):
     """Origin of the 2B-wide domain co-centred with a B-wide range at p,
     clamped into [0, extent - 2B]."""
@@ -190,7 +209,8 @@ def range_moments(I: np.ndarray, h0: np.ndarray, xs, ys, B: int) -> dict:
 
     Returns int64 arrays: sr = Sum r, srr = Sum r^2, sd = Sum d, sdd = Sum d^2
     and srd[:, e] = Sum r * T_e(d), where r is the B x B range at (x, y) and d
-    the B x B window of H0 at the domain origin halved.
+    the B x B window of H0 at the domain origin halved (of the phase-mean
+    image of the origin's parity when an origin is odd, B = 2).
     """
     I = np.asarray(I, np.int64)
     H, W = I.shape
@@ -198,8 +218,12 @@ def range_moments(I: np.ndarray, h0: np.ndarray, xs, ys, B: int) -> dict:
     ys = np.asarray(ys, np.int64)
     R = xs.size
     n = B * B
-    wx = domain_origin(xs, B, W) // 2
-    wy = domain_origin(ys, B, H) // 2
+    ox = domain_origin(xs, B, W)
+    oy = domain_origin(ys, B, H)
+    wx, wy = ox // 2, oy // 2
+    if np.any(ox % 2) or np.any(oy % 2):
+        ph = phase_means(I)
+        h0 = None
     out = {k: np.zeros(R, np.int64) for k in ("sr", "srr", "sd", "sdd")}
     out["srd"] = np.zeros((R, 8), np.int64)
     ii = np.arange(B)
@@ -208,7 +232,11 @@ def range_moments(I: np.ndarray, h0: np.ndarray, xs, ys, B: int) -> dict:
     for s in range(0, R, step):
         sl = slice(s, min(R, s + step))
         r = I[ys[sl, None, None] + ii[None, :, None], xs[sl, None, None] + ii[None, None, :]]
-        d = h0[wy[sl, None, None] + ii[None, :, None], wx[sl, None, None] + ii[None, None, :]]
+        if h0 is not None:
+            d = h0[wy[sl, None, None] + ii[None, :, None], wx[sl, None, None] + ii[None, None, :]]
+        else:
+            d = ph[(oy[sl] % 2)[:, None, None], (ox[sl] % 2)[:, None, None],
+                   wy[sl, None, None] + ii[None, :, None], wx[sl, None, None] + ii[None, None, :]]
         out["sr"][sl] = r.sum(axis=(1, 2))
         out["srr"][sl] = (r * r).sum(axis=(1, 2))
         out["sd"][sl] = d.sum(axis=(1, 2))

@@ -3,7 +3,8 @@
 A stream here is any valid set of records in the encoder's order: top tiles
 in raster order, each split by a random quadtree whose leaves follow in
 Morton order (y bit above x), every leaf a phase-1 record (random isometry,
-contrast k/8 and mean, co-centred domain) or, for B >= 8, a phase-2 record
+contrast k/8 and mean, co-centred domain) or, for B >= 8 (B >= 4 when the
+tree reaches 2 x 2), a phase-2 record
 (random contrast bits and luminances O_c inside 0..255, Sec. 3.3).  The
 decoded result of such a stream is fixed by the decoder's definition alone,
 whatever the encoder would have chosen, so these streams reach record mixes
@@ -28,7 +29,8 @@ def random_stream(width: int, height: int, b_max: int, b_min: int, seed: int,
         r["x"], r["y"], r["level"] = x, y, level
         # phase 2 stands for a range that phase 1 did not accept, so an
         # encoder never emits it at the last level (a decoder still can take it)
-        if B >= 8 and level <= 2 and (B > b_min or not bounded) and rng.random() < p_phase2:
+        # phase-2 sub-blocks are at least 4 x 4, or 2 x 2 in a tree that reaches 2 x 2
+        if B >= (4 if b_min == 2 else 8) and level <= 2 and (B > b_min or not bounded) and rng.random() < p_phase2:
             m = int(rng.integers(40, 216))
             if bounded:
                 delta = mns.PHASE2_DELTA[level + 1]

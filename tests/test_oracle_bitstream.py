@@ -136,6 +136,8 @@ def test_technique2_matches_the_papers_figures():
     ("c2 identity", lambda: synth.workload("c2"), 16, 4, [300, 200], False),
     ("pw 32", lambda: synth.piecewise_smooth(192, 256, 13, cells=40), 32, 4, [120, 90, 60], True),
     ("noise 4", lambda: synth.noise_1f(16, 24, 18), 4, 4, [], True),
+    ("c2 16->2", lambda: synth.workload("c2"), 16, 2, [300, 200, 100], False),
+    ("noise 8->2", lambda: synth.noise_1f(40, 24, 19), 8, 2, [300, 100], True),
 ])
 def test_round_trip_encoded(name, make, b_max, b_min, thr, iso):
     img = make()
@@ -149,7 +151,7 @@ def test_round_trip_encoded(name, make, b_max, b_min, thr, iso):
 
 
 @pytest.mark.parametrize("W,H,bm,bmin,seed", [(96, 160, 32, 4, 1), (160, 96, 32, 8, 2), (64, 48, 16, 4, 3),
-                                              (64, 64, 4, 4, 5), (264, 136, 8, 4, 6)])
+                                              (64, 64, 4, 4, 5), (264, 136, 8, 4, 6), (64, 48, 16, 2, 7)])
 def test_round_trip_random(W, H, bm, bmin, seed):
     r = random_stream(W, H, bm, bmin, seed, bounded=True)
     data, nbits = bs.pack(r, W, H, bm, bmin, isometries=True)

@@ -142,7 +142,7 @@ def test_moments_bruteforce():
     img = rng.integers(0, 256, (32, 48)).astype(np.uint8)
     I = img.astype(np.int64)
     h0 = mns.downsample(img)
-    for B in (4, 8, 16):
+    for B in (2, 4, 8, 16):        # B = 2: odd domain origins
         ys, xs = np.mgrid[0:32:B, 0:48:B]
         mom = mns.range_moments(I, h0, xs.ravel(), ys.ravel(), B)
         for idx, (x, y) in enumerate(zip(xs.ravel(), ys.ravel())):
@@ -184,7 +184,7 @@ def _brute_fit(r, d):
     return e, k, m, err // n                     # S = 64 n E
 
 
-@pytest.mark.parametrize("B", [4, 8])
+@pytest.mark.parametrize("B", [2, 4, 8])
 def test_fit_equals_bruteforce_grid(B):
     rng = np.random.default_rng(10 + B)
     cases = []
@@ -246,7 +246,7 @@ def test_ramp_has_zero_error_everywhere():
     img = synth.ramp(64, 64)
     I = img.astype(np.int64)
     h0 = mns.downsample(img)
-    for B in (32, 16, 8, 4):
+    for B in (32, 16, 8, 4, 2):
         ys, xs = np.mgrid[0:64:B, 0:64:B]
         mom = mns.range_moments(I, h0, xs.ravel(), ys.ravel(), B)
         e, k, m, S = mns.fit_phase1(mom, B * B)
@@ -294,7 +294,7 @@ def _preorder(rec, W, H, b_max):
         if (x, y, B) in leaves:
             order.append(leaves[(x, y, B)])
             return
-        assert B > 4, "missing leaf"
+        assert B > 2, "missing leaf"
         b = B // 2
         for ox, oy in ((0, 0), (b, 0), (0, b), (b, b)):
             visit(x + ox, y + oy, b)
@@ -308,6 +308,8 @@ def _preorder(rec, W, H, b_max):
 @pytest.mark.parametrize("name,b_max,b_min,thr", [
     ("c1", 8, 4, [600]),
     ("c2", 16, 4, [300, 200]),
+    ("c1", 8, 2, [600, 300]),
+    ("c2", 16, 2, [300, 200, 100]),     # the paper's four levels, 16 x 16 to 2 x 2
 ])
 def test_stream_structure_and_decisions(name, b_max, b_min, thr):
     img = synth.workload(name)
@@ -390,7 +392,12 @@ def test_validation():
     with pytest.raises(ValueError):
         mns.encode(img, 64, 4, [1, 1, 1, 1])
     with pytest.raises(ValueError):
-        mns.encode(img, 8, 2, [1, 1])
+        mns.encode(img, 32, 2, [1, 1, 1, 1])   # five levels: more than two level bits hold
+    with pytest.raises(ValueError):
+        mns.encode(img, 8, 1, [1, 1, 1])
+    with pytest.raises(ValueError):
+        mns.encode(img, 2, 2, [])
+    assert mns.encode(img, 16, 2, [1, 1, 1]).size > 0
     with pytest.raises(ValueError):
         mns.encode(np.zeros((60, 64), np.uint8), 8, 4, [1])
     with pytest.raises(ValueError):
@@ -535,6 +542,18 @@ def test_decoder_one_step_by_definition(c1_stream):
     img, rec = c1_stream
     assert np.any(rec["flags"] & 1) and np.any(rec["iso"] >= 4)
     rng = np.random.default_rng(11)
+    start = rng.integers(0, 256, (64, 64)).astype(np.uint8)
+    want = _decode_step_by_definition(rec, start, 8)
+    np.testing.assert_array_equal(decode.decode(rec, 64, 64, 8, 1, start=start).astype(np.int64), want)
+
+
+def test_decoder_one_step_by_definition_2x2():
+    # a tree down to 2 x 2 (odd domain origins, phase 2 over 2 x 2 sub-blocks)
+    img = synth.workload("c1")
+    rec = mns.encode(img, 8, 2, [600, 300])
+    assert np.any(rec["level"] == 2) and np.any((rec["flags"] & 1) & (rec["level"] == 1))
+    assert np.any(rec["dx"] % 2)
+    rng = np.random.default_rng(12)
     start = rng.integers(0, 256, (64, 64)).astype(np.uint8)
     want = _decode_step_by_definition(rec, start, 8)
     np.testing.assert_array_equal(decode.decode(rec, 64, 64, 8, 1, start=start).astype(np.int64), want)
