@@ -125,7 +125,11 @@ typedef struct fe_transform {
 /*
  * Encoder parameters.
  *   b_max, b_min  largest and smallest range side: powers of two with
- *                 4 <= b_min <= b_max <= 32 (at most four levels, Sec. 3.3).
+ *                 2 <= b_min <= b_max, 4 <= b_max <= 32 and at most four
+ *                 levels (two level bits, Sec. 3.3; the paper's tree is
+ *                 16 -> 2).  b_min = 2 is taken by fe_encode only (MNS or
+ *                 no-search, b_max 4, 8 or 16; not the batch, plan, server,
+ *                 exhaustive or local-search paths).
  *   n_thr         number of thresholds = L - 1, L = log2(b_max/b_min) + 1.
  *   flags         FE_PHASE2, FE_FULL_SEARCH, FE_IDENTITY_ONLY (MNS only),
  *                 FE_LOCAL_SEARCH (not with FE_FULL_SEARCH).
@@ -215,6 +219,9 @@ fe_status fe_range_moments(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, ui
  * Encode one image (MNS, Sec. 3 and 3.1-3.3; or the exhaustive baseline
  * with FE_FULL_SEARCH).  d_img is W x H uint8 with row pitch `stride`
  * bytes (4-byte aligned).  Writes the stream to d_out[0 .. *n_out).
+ * With b_min = 2 the 2 x 2 ranges take their co-centred domains at odd
+ * origins (x - 1); a separate encoder (one wave per top tile, domain means
+ * formed from pixels) runs that tree, with the same stream format.
  * Waits for the stream to finish (the count is needed on the host).
  * FE_ERR_CAPACITY if cap is smaller than the stream; *n_out then holds
  * the needed count and d_out is left unspecified.  cap =
@@ -288,7 +295,8 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
  * of b_max (each at least 2 b_max), d_out is 4-byte aligned, and the stream
  * lists the tiles in raster order with each tile's transforms partitioning
  * it in Morton order (the order fe_encode writes) with co-centred domains
- * (Sec. 3.1), and its plan (2.3 KB per 64 x 64-pixel block, kept in the
+ * (Sec. 3.1) and maps no block under 4 x 4 pixels (no 2 x 2 range, no
+ * phase-2 transform of side 4), and its plan (2.3 KB per 64 x 64-pixel block, kept in the
  * context) can be allocated.  The record decoder (one wave per transform)
  * runs any valid stream.  fe_decode_set_mode selects FE_DECODE_AUTO (the default: tiles
  * when allowed) or FE_DECODE_RECORDS for a context; fe_decode_last returns
@@ -297,6 +305,23 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
 enum { FE_DECODE_AUTO = 0, FE_DECODE_RECORDS = 1, FE_DECODE_TILES = 2 };
 fe_status fe_decode_set_mode(fe_ctx* ctx, int mode);
 int fe_decode_last(const fe_ctx* ctx);
+
+/*
+ * Zoom decoding (Sec. 1: the stored maps do not depend on the resolution).
+ * Decodes a stream encoded for a W x H image (top blocks b_max) at `zoom`
+ * times the size: every transform's range and domain origins are multiplied
+ * by zoom and the maps are iterated on a zoom W x zoom H image with top blocks
+ * of zoom b_max, as fe_decode does (same arithmetic, same choice between the
+ * two decoders; a co-centred domain stays co-centred).  zoom is a power of
+ * two with zoom * b_max <= 32 (1 decodes at the native size); zoom W and
+ * zoom H are at most 65536.  d_start (or mid-grey when NULL) and d_out are
+ * zoom W x zoom H, dense.  The transforms are checked against the native
+ * W x H image first (FE_ERR_INVALID as in fe_decode); the zoomed copy lives
+ * in the context (16 bytes per transform).  Waits for the check.
+ */
+fe_status fe_decode_zoom(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t width,
+                         uint32_t height, uint32_t b_max, uint32_t zoom, uint32_t iters,
+                         const uint8_t* d_start, uint8_t* d_out, void* stream);
 
 /*
  * The compressed file (Sec. 3.3; Technique 2, Sec. 3.4).  A 64-bit header

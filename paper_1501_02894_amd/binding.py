@@ -84,6 +84,7 @@ _SIGNATURES = {
     "fe_decode": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
     "fe_decode_set_mode": (ctypes.c_int, [_VP, ctypes.c_int]),
     "fe_decode_last": (ctypes.c_int, [_VP]),
+    "fe_decode_zoom": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _U32, _VP, _VP, _VP]),
     "fe_pack_bound": (_SZ, [_SZ]),
     "fe_pack": (ctypes.c_int, [_VP, _VP, _SZ, _U32, _U32, _U32, _U32, _U32, _VP, _SZ, ctypes.POINTER(ctypes.c_uint64),
                                _VP]),
@@ -303,6 +304,19 @@ def fe_decode(ctx: int, transforms, width: int, height: int, b_max: int, iters: 
     n = int(transforms.shape[0])
     _check(load().fe_decode(ctx, _ptr(transforms), n, width, height, b_max, iters, _ptr(start), _ptr(out),
                             _stream(stream)))
+    return out
+
+
+def fe_decode_zoom(ctx: int, transforms, width: int, height: int, b_max: int, zoom: int, iters: int, start=None,
+                   out=None, stream=None):
+    """Decode a stream of a width x height image at zoom times the size; the
+    result is (zoom height, zoom width)."""
+    import torch
+    if out is None:
+        out = torch.empty((height * zoom, width * zoom), dtype=torch.uint8, device=transforms.device)
+    n = int(transforms.shape[0])
+    _check(load().fe_decode_zoom(ctx, _ptr(transforms), n, width, height, b_max, zoom, iters, _ptr(start),
+                                 _ptr(out), _stream(stream)))
     return out
 
 
@@ -571,6 +585,9 @@ class Context:
 
     def decode(self, transforms, width, height, b_max, iters, start=None, **kw):
         return fe_decode(self.handle, transforms, width, height, b_max, iters, start=start, **kw)
+
+    def decode_zoom(self, transforms, width, height, b_max, zoom, iters, start=None, **kw):
+        return fe_decode_zoom(self.handle, transforms, width, height, b_max, zoom, iters, start=start, **kw)
 
     def decode_mode(self, mode):
         fe_decode_set_mode(self.handle, mode)

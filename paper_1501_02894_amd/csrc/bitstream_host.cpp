@@ -47,7 +47,8 @@ fe_status fe_unpack(const uint8_t* h_bits, uint64_t n_bits, fe_transform* h_out,
   const uint32_t reserved = rd.get(25);
   if (!rd.ok) return fe::fail(FE_ERR_INVALID, "the file is shorter than its header");
   if (reserved) return fe::fail(FE_ERR_INVALID, "reserved header bits are set");
-  if (b_min < 4 || b_max > 32 || b_min > b_max || W % b_max || H % b_max || W < 2 * b_max || H < 2 * b_max)
+  if (b_min < 2 || b_max < 4 || b_max > 32 || b_min > b_max || fe::levels_of(b_max, b_min) > 4 || W % b_max ||
+      H % b_max || W < 2 * b_max || H < 2 * b_max)
     return fe::fail(FE_ERR_INVALID, "header: %ux%u image with blocks %u -> %u does not tile", W, H, b_max, b_min);
   if (info) *info = fe_stream_info{W, H, b_max, b_min, iso ? FE_PACK_ISOMETRY : 0u};
   const int L = fe::levels_of(b_max, b_min);

@@ -60,14 +60,14 @@ __device__ __forceinline__ bool bad_record(const Fields& f, int W, int H, int bm
   if (f.flags > 1 || bmax < 4) return true;
   if (f.level > 3) return true;
   const int B = bmax >> f.level;
-  if (B < 4 || (f.x % B) || (f.y % B) || f.x + B > W || f.y + B > H) return true;
+  if (B < 2 || (f.x % B) || (f.y % B) || f.x + B > W || f.y + B > H) return true;
   if (f.flags == 0) {
     if (f.iso > 7 || f.s_idx > 7) return true;
     if (f.dx + 2 * B > W || f.dy + 2 * B > H) return true;
     if (f.d0 || f.d1 || f.d2) return true;
     return false;
   }
-  if (B < 8 || f.level > 2 || f.iso != 0 || f.s_idx > 15) return true;
+  if (B < 4 || f.level > 2 || f.iso != 0 || f.s_idx > 15) return true;
   const int O0 = f.lum + f.d0, O1 = f.lum + f.d1, O2 = f.lum + f.d2;
   const int O3 = 4 * f.lum - O0 - O1 - O2;
   if (O0 < 0 || O0 > 255 || O1 < 0 || O1 > 255 || O2 < 0 || O2 > 255 || O3 < 0 || O3 > 255) return true;
@@ -78,6 +78,24 @@ __global__ __launch_bounds__(256) void check_kernel(DecodeArgs a, uint32_t* bad)
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   if (bad_record(unpack(a.recs[i]), (int)a.width, (int)a.height, (int)a.b_max)) atomicAdd(bad, 1u);
+}
+
+// Zoom (the maps are resolution independent, Sec. 1): check each transform
+// against the native image, then write it with range and domain origins
+// multiplied by z.  Levels, contrasts and luminances do not change; the
+// result is decoded as a z W x z H image with top blocks of z b_max, where
+// the co-centred domains stay co-centred (the clamp commutes with the
+// scaling).  A transform that fails the native check is counted and written
+// with its fields masked, never decoded.
+__global__ __launch_bounds__(256) void zoom_kernel(DecodeArgs a, uint32_t z, uint4* __restrict__ out,
+                                                   uint32_t* bad) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint4 w = a.recs[i];
+  if (bad_record(unpack(w), (int)a.width, (int)a.height, (int)a.b_max)) atomicAdd(bad, 1u);
+  const uint32_t x = (w.x & 0xffffu) * z, y = (w.x >> 16) * z;
+  const uint32_t dx = (w.y & 0xffffu) * z, dy = (w.y >> 16) * z;
+  out[i] = make_uint4((x & 0xffffu) | ((y & 0xffffu) << 16), (dx & 0xffffu) | ((dy & 0xffffu) << 16), w.z, w.w);
 }
 
 // 16 bytes per lane: one 16-byte copy when both pointers allow it, else
@@ -177,37 +195,45 @@ __global__ __launch_bounds__(256) void iter_kernel(DecodeArgs a, const uint8_t* 
 
 // ---------------------------------------------------------------- tiles
 // Tile-ordered decoding.  Streams whose records partition every top tile in
-// order (consecutive Morton intervals of 4 x 4-pixel cells, y bit above x,
-// tiles in raster order) and use the co-centred domains are decoded one
-// block of 128 x 128 pixels per workgroup: the block's domain region of
-// the iterate is reduced to H0 in LDS once, every record's domain sum comes
-// from there, and the output is written four pixels at a time.  Any other
-// stream uses iter_kernel.
+// order (consecutive Morton intervals of 2 x 2-pixel cells, y bit above x,
+// tiles in raster order), use the co-centred domains and map blocks of at
+// least 4 x 4 pixels are decoded one block of 128 x 128 pixels per
+// workgroup: the block's domain region of the iterate is reduced to H0 in
+// LDS once, every record's domain sum comes from there, and the output is
+// written four pixels at a time.  Any other stream uses iter_kernel.
 
 __device__ __forceinline__ int cell_morton(int cx, int cy) {
   int code = 0;
 #pragma unroll
-  for (int bit = 0; bit < 3; ++bit) code |= (((cx >> bit) & 1) << (2 * bit)) | (((cy >> bit) & 1) << (2 * bit + 1));
+  for (int bit = 0; bit < 4; ++bit) code |= (((cx >> bit) & 1) << (2 * bit)) | (((cy >> bit) & 1) << (2 * bit + 1));
   return code;
 }
 
 __device__ __forceinline__ int cocentred(int p, int B, int extent) { return clampi(p - B / 2, 0, extent - 2 * B); }
 
 // One lane per record: the first record of each tile, and whether the
-// stream meets the conditions above (flag set when it does not).
+// stream meets the conditions above: bit 0 of *flag is set when the stream
+// is not in encoder order with co-centred domains, bit 1 when it maps
+// blocks under 4 x 4 pixels (the 2 x 2 level: phase-1 ranges of side 2,
+// phase-2 ranges of side 4), which the tile decoder does not take.
 __global__ __launch_bounds__(256) void tile_setup_kernel(DecodeArgs a, uint32_t* tile_start, uint32_t* flag) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int W = (int)a.width, H = (int)a.height, bm = (int)a.b_max;
-  const int tiles_x = W / bm, ntiles = tiles_x * (H / bm), cells = (bm / 4) * (bm / 4);
+  const int tiles_x = W / bm, ntiles = tiles_x * (H / bm), cells = (bm / 2) * (bm / 2);
   auto info = [&](uint64_t k, int& tile, int& key, int& end, bool& centred) {
     const Fields f = unpack(a.recs[k]);
     const int B = bm >> f.level;
     tile = (f.y / bm) * tiles_x + f.x / bm;
-    key = cell_morton((f.x % bm) >> 2, (f.y % bm) >> 2);
-    end = key + (B >> 2) * (B >> 2);
+    key = cell_morton((f.x % bm) >> 1, (f.y % bm) >> 1);
+    end = key + (B >> 1) * (B >> 1);
     centred = f.dx == cocentred(f.x, B, W) && f.dy == cocentred(f.y, B, H);
   };
+  {
+    const Fields f = unpack(a.recs[i]);
+    const int B = bm >> f.level;
+    if (B < 4 || (f.flags != 0 && B < 8)) atomicOr(flag, 2u);
+  }
   int tile, key, end;
   bool centred;
   info(i, tile, key, end, centred);
@@ -472,6 +498,12 @@ __global__ __launch_bounds__(256) void dec_iter_kernel(DecodeArgs a, uint32_t n_
 hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   hipLaunchKernelGGL(check_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_zoom(const DecodeArgs& a, uint32_t z, uint4* out, uint32_t* bad, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zoom_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, z, out, bad);
   return hipGetLastError();
 }
 

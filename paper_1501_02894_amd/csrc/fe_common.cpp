@@ -36,9 +36,10 @@ fe_status check_params(const fe_params* p) {
   if (!p) return fail(FE_ERR_INVALID, "params is NULL");
   if (!is_pow2(p->b_max) || !is_pow2(p->b_min))
     return fail(FE_ERR_INVALID, "b_max (%u) and b_min (%u) must be powers of two", p->b_max, p->b_min);
-  if (p->b_min < 4 || p->b_min > p->b_max || p->b_max > 32)
-    return fail(FE_ERR_INVALID, "need 4 <= b_min <= b_max <= 32 (got %u, %u)", p->b_min, p->b_max);
+  if (p->b_min < 2 || p->b_min > p->b_max || p->b_max < 4 || p->b_max > 32)
+    return fail(FE_ERR_INVALID, "need 2 <= b_min <= b_max, 4 <= b_max <= 32 (got %u, %u)", p->b_min, p->b_max);
   const int L = levels_of(p->b_max, p->b_min);
+  if (L > 4) return fail(FE_ERR_INVALID, "%u -> %u is %d levels; two level bits hold four", p->b_max, p->b_min, L);
   if (p->n_thr != (uint32_t)(L - 1))
     return fail(FE_ERR_INVALID, "n_thr must be %d (one per level except the last), got %u", L - 1, p->n_thr);
   if (p->flags & ~(FE_PHASE2 | FE_FULL_SEARCH | FE_IDENTITY_ONLY | FE_LOCAL_SEARCH))

@@ -66,6 +66,8 @@ struct fe_ctx {
   size_t dec_pieces_n = 0;
   uint64_t* pack_chunk = nullptr;     // bitstream: chunk sums, then chunk bases
   size_t pack_chunk_n = 0;
+  uint4* zoom_recs = nullptr;         // zoom decoding: the scaled transforms
+  size_t zoom_recs_n = 0;
   bool last_decode_tiled = false;     // which decoder the last fe_decode ran
   int decode_mode = FE_DECODE_AUTO;
   fe::TileShape shape_override[33][5] = {};
@@ -234,6 +236,7 @@ fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_par
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
   if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
+  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "b_min 2 is encoded by fe_encode only");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
   for (uint32_t k = 0; k < n_imgs; ++k) {
     if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
@@ -450,6 +453,64 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
   return FE_OK;
 }
 
+// MNS quadtree down to 2 x 2 ranges (b_min = 2) of one image: one launch
+// over the top tiles, then the ordering kernels over one-tile blocks.
+fe_status encode_fine(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride, const fe_params* p,
+                      fe_transform* d_out, size_t cap, size_t* n_out, hipStream_t s) {
+  if (p->b_max > 16)
+    return fe::fail(FE_ERR_INVALID, "b_min 2 needs b_max <= 16 (got %u)", p->b_max);
+  const int L = fe::levels_of(p->b_max, p->b_min);
+  const int cells = 1 << (2 * (L - 1));
+  const uint64_t tiles = (uint64_t)(w / p->b_max) * (h / p->b_max);
+  fe_status st;
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
+  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
+  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
+  if ((st = ensure(ctx->offsets, ctx->offsets_n, 2, "offsets")) != FE_OK) return st;
+  fe::ImgDev im{};
+  im.data = d_img;
+  im.width = w;
+  im.height = h;
+  im.stride = stride;
+  im.tiles_x = w / p->b_max;
+  im.tiles_y = h / p->b_max;
+  im.groups_x = im.tiles_x;
+  im.groups_y = im.tiles_y;
+  im.wg_first = 0;
+  im.tile_first = 0;
+  if ((st = upload_table(ctx, &im, 1, tiles, s)) != FE_OK) return st;
+  fe::FineArgs a{};
+  a.img = d_img;
+  a.w = w;
+  a.h = h;
+  a.stride = stride;
+  a.tiles_x = w / p->b_max;
+  a.tiles = (uint32_t)tiles;
+  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
+  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
+  a.staging = ctx->staging;
+  a.masks = ctx->masks;
+  {
+    Timed t(ctx, FE_TIMING_ENCODE, s);
+    FE_HIP(fe::launch_mns_fine((int)p->b_max, a, s), "encode kernel launch");
+  }
+  {
+    Timed t(ctx, FE_TIMING_SCATTER, s);
+    FE_HIP(fe::launch_scatter(ctx->d_table, 1, nullptr, tiles, cells, fe::TileShape{1, 1}, ctx->masks,
+                              ctx->chunk_sum, ctx->chunk_base, ctx->staging, reinterpret_cast<uint4*>(d_out),
+                              (uint64_t)cap, ctx->offsets, s),
+           "scatter launch");
+  }
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->offsets + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "count");
+  FE_HIP(hipStreamSynchronize(s), "encode");
+  *n_out = (size_t)ctx->h_scalars[0];
+  if (*n_out > cap) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
+  return FE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -512,6 +573,7 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->dec_cells);
   (void)hipFree(c->dec_pieces);
   (void)hipFree(c->pack_chunk);
+  (void)hipFree(c->zoom_recs);
   if (c->ev) {
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
       if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -556,8 +618,11 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, u
   if ((uintptr_t)d_img & 3) return fe::fail(FE_ERR_SHAPE, "image must be 4-byte aligned");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
   DeviceGuard g(ctx->device);
-  if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH))
+  if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) {
+    if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "the exhaustive and local searches need b_min >= 4");
     return encode_full_search(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
+  }
+  if (p->b_min < 4) return encode_fine(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
   fe_image_desc one{d_img, w, h, stride, 0};
   return encode_images(ctx, &one, 1, p, d_out, cap, nullptr, n_out, (hipStream_t)stream);
 }
@@ -572,16 +637,14 @@ fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_i
   return encode_images(ctx, h_imgs, n_imgs, p, d_out, cap, d_offsets, n_out, (hipStream_t)stream);
 }
 
-fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
-                    uint32_t iters, const uint8_t* d_start, uint8_t* d_out, void* stream) {
-  fe::clear_error();
-  if (!ctx || !d_out || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
-  if (!fe::is_pow2(b_max) || b_max < 4 || b_max > 32) return fe::fail(FE_ERR_INVALID, "bad b_max %u", b_max);
-  if (w < 2 || h < 2 || w > 65536 || h > 65536) return fe::fail(FE_ERR_SHAPE, "bad image size %ux%u", w, h);
-  if ((uintptr_t)d_t & 15) return fe::fail(FE_ERR_INVALID, "transforms must be 16-byte aligned");
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  fe::DecodeArgs a{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
+namespace {
+
+// The decoder after argument checks; a.recs holds n 16-byte transforms on
+// the device, the current device is ctx's.
+fe_status decode_body(fe_ctx* ctx, const fe::DecodeArgs& a, uint32_t iters, const uint8_t* d_start, uint8_t* d_out,
+                      hipStream_t s) {
+  const uint64_t n = a.n;
+  const uint32_t w = a.width, h = a.height, b_max = a.b_max;
   // Tile-ordered decoding needs whole top tiles, room for a domain of the
   // top size, word-aligned rows and a stream that partitions every tile in
   // stream order with co-centred domains (checked on the device below).
@@ -629,6 +692,45 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, 
   return FE_OK;
 }
 
+}  // namespace
+
+fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
+                    uint32_t iters, const uint8_t* d_start, uint8_t* d_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_out || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (!fe::is_pow2(b_max) || b_max < 4 || b_max > 32) return fe::fail(FE_ERR_INVALID, "bad b_max %u", b_max);
+  if (w < 2 || h < 2 || w > 65536 || h > 65536) return fe::fail(FE_ERR_SHAPE, "bad image size %ux%u", w, h);
+  if ((uintptr_t)d_t & 15) return fe::fail(FE_ERR_INVALID, "transforms must be 16-byte aligned");
+  DeviceGuard g(ctx->device);
+  const fe::DecodeArgs a{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
+  return decode_body(ctx, a, iters, d_start, d_out, (hipStream_t)stream);
+}
+
+fe_status fe_decode_zoom(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
+                         uint32_t zoom, uint32_t iters, const uint8_t* d_start, uint8_t* d_out, void* stream) {
+  fe::clear_error();
+  if (!ctx || !d_out || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  if (!fe::is_pow2(b_max) || b_max < 4 || b_max > 32) return fe::fail(FE_ERR_INVALID, "bad b_max %u", b_max);
+  if (!fe::is_pow2(zoom) || zoom * b_max > 32)
+    return fe::fail(FE_ERR_INVALID, "zoom %u: it must be a power of two with zoom * b_max <= 32", zoom);
+  if (w < 2 || h < 2 || (uint64_t)w * zoom > 65536 || (uint64_t)h * zoom > 65536)
+    return fe::fail(FE_ERR_SHAPE, "bad image size %ux%u at zoom %u", w, h, zoom);
+  if ((uintptr_t)d_t & 15) return fe::fail(FE_ERR_INVALID, "transforms must be 16-byte aligned");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  fe_status st = ensure(ctx->zoom_recs, ctx->zoom_recs_n, std::max<size_t>(n, 1), "zoomed transforms");
+  if (st != FE_OK) return st;
+  const fe::DecodeArgs native{reinterpret_cast<const uint4*>(d_t), (uint64_t)n, w, h, b_max, 0};
+  FE_HIP(fe::launch_zero_u32(ctx->flags, 2, s), "zero flags");
+  FE_HIP(fe::launch_decode_zoom(native, zoom, ctx->zoom_recs, ctx->flags, s), "zoom launch");
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "flag read-back");
+  FE_HIP(hipStreamSynchronize(s), "transform check");
+  const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
+  if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms are out of range for a %ux%u image", bad, w, h);
+  const fe::DecodeArgs a{ctx->zoom_recs, (uint64_t)n, w * zoom, h * zoom, b_max * zoom, 0};
+  return decode_body(ctx, a, iters, d_start, d_out, s);
+}
+
 size_t fe_pack_bound(size_t n) { return 8 + ((33 * (uint64_t)n + 63) / 64) * 8; }
 
 fe_status fe_pack(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, uint32_t h, uint32_t b_max,
@@ -637,7 +739,8 @@ fe_status fe_pack(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, ui
   if (!ctx || !d_out || !n_bits || (n && !d_t)) return fe::fail(FE_ERR_INVALID, "NULL argument");
   if (((uintptr_t)d_out & 7) || ((uintptr_t)d_t & 15)) return fe::fail(FE_ERR_INVALID, "misaligned buffer");
   if (flags & ~FE_PACK_ISOMETRY) return fe::fail(FE_ERR_INVALID, "unknown pack flags 0x%x", flags);
-  if (!fe::is_pow2(b_max) || !fe::is_pow2(b_min) || b_min < 4 || b_max > 32 || b_min > b_max)
+  if (!fe::is_pow2(b_max) || !fe::is_pow2(b_min) || b_min < 2 || b_max < 4 || b_max > 32 || b_min > b_max ||
+      fe::levels_of(b_max, b_min) > 4)
     return fe::fail(FE_ERR_INVALID, "bad block sizes %u, %u", b_max, b_min);
   if (w % b_max || h % b_max || w < 2 * b_max || h < 2 * b_max || w > 65536 || h > 65536)
     return fe::fail(FE_ERR_SHAPE, "image %ux%u does not tile with b_max %u", w, h, b_max);
@@ -667,7 +770,7 @@ fe_status fe_pack(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t w, ui
   FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->flags, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "pack read-back");
   FE_HIP(hipStreamSynchronize(s), "pack");
   const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
-  const uint32_t disorder = (uint32_t)(ctx->h_scalars[0] >> 32);
+  const uint32_t disorder = (uint32_t)(ctx->h_scalars[0] >> 32) & 1u;   // bit 1 (2 x 2 blocks) is fine here
   const uint64_t bits = ctx->h_scalars[1];
   if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms have fields their codes cannot hold", bad);
   if (disorder) return fe::fail(FE_ERR_INVALID, "the stream is not in encoder order with co-centred domains");
@@ -737,6 +840,7 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
   if (!ctx || !gx || !gy || !ms || reps == 0) return fe::fail(FE_ERR_INVALID, "bad arguments");
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
+  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "b_min 2 has no tile shapes to tune");
   const int L = fe::levels_of(p->b_max, p->b_min);
   fe::TileShape shapes[16];
   const int k = fe::encode_shapes((int)p->b_max, L, shapes, 16);

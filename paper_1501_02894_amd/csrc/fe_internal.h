@@ -97,6 +97,22 @@ struct DecodeArgs {
   uint32_t width, height, b_max, pad;
 };
 hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t stream);
+// Encoder of quadtrees that reach 2 x 2 ranges (b_min = 2, b_max 4, 8 or
+// 16): one wave per top tile of one image; records go to staging[tile *
+// cells + Morton cell of 2 x 2 units], the tile's occupancy to masks[tile].
+struct FineArgs {
+  const uint8_t* img;
+  uint32_t w, h, stride;
+  uint32_t tiles_x, tiles;
+  uint32_t phase2, identity_only;
+  uint32_t thr[4];
+  uint4* staging;
+  uint64_t* masks;
+};
+hipError_t launch_mns_fine(int b_max, const FineArgs& a, hipStream_t stream);
+
+// Native check of a.recs (count into *bad) and the records zoomed by z into out.
+hipError_t launch_decode_zoom(const DecodeArgs& a, uint32_t z, uint4* out, uint32_t* bad, hipStream_t stream);
 hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint32_t h,
                               hipStream_t stream);
 hipError_t launch_decode_iter(const DecodeArgs& a, const uint8_t* cur, uint8_t* nxt,

@@ -47,7 +47,8 @@ def _oracle_ok(w, h, b_max, b_min, n_thr):
 
 def test_validation_agrees_with_oracle(lib):
     sizes = [(64, 64), (48, 64), (16, 16), (8, 8), (60, 64), (32, 40), (96, 32), (4, 4), (128, 8)]
-    blocks = [(4, 4), (8, 4), (16, 4), (16, 8), (32, 4), (32, 16), (64, 8), (8, 2), (6, 3), (8, 16)]
+    blocks = [(4, 4), (8, 4), (16, 4), (16, 8), (32, 4), (32, 16), (64, 8), (8, 2), (6, 3), (8, 16), (16, 2),
+              (32, 2), (4, 2), (2, 2), (8, 1)]
     for (w, h), (bmax, bmin) in itertools.product(sizes, blocks):
         for n_thr in range(0, 5):
             p = fb.fe_params()
@@ -101,6 +102,7 @@ def test_null_arguments(lib):
     n = ctypes.c_size_t(0)
     assert lib.fe_encode(None, None, 64, 64, 64, ctypes.byref(p), None, 0, ctypes.byref(n), None) == fb.FE_ERR_INVALID
     assert lib.fe_decode(None, None, 0, 64, 64, 16, 1, None, None, None) == fb.FE_ERR_INVALID
+    assert lib.fe_decode_zoom(None, None, 0, 64, 64, 16, 2, 1, None, None, None) == fb.FE_ERR_INVALID
     lib.fe_destroy(None)
     assert lib.fe_timing_select(None, 1) == fb.FE_ERR_INVALID
     assert lib.fe_decode_set_mode(None, 0) == fb.FE_ERR_INVALID

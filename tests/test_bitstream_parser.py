@@ -15,6 +15,8 @@ from test_oracle_bitstream import tiny_mixed, tiny_phase1, to_bytes
     ("c1", lambda: synth.workload("c1"), 8, 4, [600], True),
     ("c2", lambda: synth.workload("c2"), 16, 4, [300, 200], True),
     ("c2 identity", lambda: synth.workload("c2"), 16, 4, [300, 200], False),
+    ("c2 16->2", lambda: synth.workload("c2"), 16, 2, [300, 200, 100], False),
+    ("c1 8->2", lambda: synth.workload("c1"), 8, 2, [600, 300], True),
     ("pw 32", lambda: synth.piecewise_smooth(192, 256, 13, cells=40), 32, 4, [120, 90, 60], True),
     ("noise 4", lambda: synth.noise_1f(16, 24, 18), 4, 4, [], True),
 ])
@@ -29,7 +31,7 @@ def test_parser_reads_oracle_files(name, make, b_max, b_min, thr, iso):
 
 
 @pytest.mark.parametrize("W,H,bm,bmin,seed", [(96, 160, 32, 4, 1), (160, 96, 32, 8, 2), (64, 48, 16, 4, 3),
-                                              (264, 136, 8, 4, 6)])
+                                              (264, 136, 8, 4, 6), (64, 48, 16, 2, 7), (40, 24, 4, 2, 8)])
 def test_parser_random_streams(W, H, bm, bmin, seed):
     r = random_stream(W, H, bm, bmin, seed, bounded=True)
     data, nbits = bs.pack(r, W, H, bm, bmin, isometries=True)
