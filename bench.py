@@ -260,6 +260,40 @@ def bench_bitstream(fb, ctx, img, b_max, b_min, thr, reps=5):
     return res
 
 
+def bench_paper_tree(fb, ctx, img, thr4, thr2, reps=5):
+    """The paper's quadtree, 16 x 16 down to 2 x 2 (Sec. 3.3), against the
+    16 -> 4 tree, both with the paper's identity-only codes: encode kernel
+    time (HIP events), call wall time, transforms, file size and the PSNR of
+    12 decoder iterations from grey; then zoom decoding (Sec. 1) of the
+    16 -> 4 stream at 1x and 2x (decode kernel time per iteration)."""
+    import torch
+    H, W = img.shape
+    t = torch.from_numpy(img).cuda()
+    res = {}
+    for name, b_min, thr in (("16to4", 4, thr4), ("16to2", 2, thr2)):
+        p = fb.make_params(16, b_min, thr, identity_only=True)
+        out = torch.empty((fb.fe_max_transforms(W, H, b_min), 16), dtype=torch.uint8, device="cuda")
+        recs = fb.fe_encode(ctx.handle, t, p, out=out)
+        kms, launches, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE,
+                                           lambda: fb.fe_encode(ctx.handle, t, p, out=out), reps)
+        _, nbits = fb.fe_pack(ctx.handle, recs, W, H, 16, b_min, isometry=False)
+        dec = fb.fe_decode(ctx.handle, recs, W, H, 16, 12).cpu().numpy().astype(np.float64)
+        mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
+        res[name] = {"transforms": int(recs.shape[0]), "encode_kernel_ms": kms, "call_ms": wall,
+                     "bpp": nbits / (W * H), "psnr_db_12_iters": 10.0 * np.log10(255.0 ** 2 / mse),
+                     "decoder": "tiles" if ctx.decode_last() == fb.FE_DECODE_TILES else "records",
+                     "pixels_per_s": W * H / (kms / 1e3)}
+        if b_min == 4:
+            zoom = {}
+            for z in (1, 2):
+                fn = lambda: fb.fe_decode_zoom(ctx.handle, recs, W, H, 16, z, 12)
+                dms, dl, dwall = timed_kernel(fb, ctx, fb.FE_TIMING_DECODE, fn, 3)
+                zoom[f"x{z}"] = {"side": W * z, "iter_kernel_ms": dms, "call_ms": dwall,
+                                 "decoder": "tiles" if ctx.decode_last() == fb.FE_DECODE_TILES else "records"}
+            res["zoom_16to4"] = zoom
+    return res
+
+
 def bench_tradeoff(fb, ctx, images, b_max=16, b_min=4, reps=5):
     """No-search (phase 1 only) against MNS (Technique 1 on) over a sweep of
     thresholds, with the paper's codes (identity only, 14-bit phase 1): per
@@ -414,6 +448,8 @@ def main():
                     help="only decode C3 (4096^2, 32 -> 4) with both decoders (a profiling workload)")
     ap.add_argument("--tradeoff", action="store_true",
                     help="only the no-search vs MNS sweep (bpp, PSNR, time) on two 512^2 images")
+    ap.add_argument("--paper-tree", action="store_true",
+                    help="only the 16 -> 2 tree against 16 -> 4 on C2 and C3, and zoom decoding")
     ap.add_argument("--fullsearch-only", action="store_true",
                     help="only the exhaustive-search encode of C2 (512^2, 16 -> 4) (a profiling workload)")
     args = ap.parse_args()
@@ -438,6 +474,15 @@ def main():
         ctx.close()
         print(json.dumps({"workload": "no-search vs MNS, 512^2, 16 -> 4, identity-only codes", "points": pts}),
               flush=True)
+        return
+    if args.paper_tree:
+        c2, c3 = pooled(_gen_named, ["c2", "c3"], 2)
+        ctx = fb.Context(0)
+        res = {"c2": bench_paper_tree(fb, ctx, c2, [300, 200], [300, 200, 100]),
+               "c3": bench_paper_tree(fb, ctx, c3, [150, 100], [150, 100, 64])}
+        ctx.close()
+        print(json.dumps({"workload": "16 -> 2 vs 16 -> 4 trees on C2 (512^2) and C3 (4096^2), zoom decoding",
+                          "paper_tree": res}), flush=True)
         return
     if args.fullsearch_only:
         from paper_1501_02894_amd import synth
@@ -647,6 +692,8 @@ def main():
         result["c2_localsearch"] = bench_localsearch(fb, ctx, c2, 16, 4, [300, 200])
         result["bitstream"] = {"c2": bench_bitstream(fb, ctx, c2, 16, 4, [300, 200]),
                                "c3": bench_bitstream(fb, ctx, c3, 32, 4, [150, 100, 64])}
+        result["paper_tree"] = {"c2": bench_paper_tree(fb, ctx, c2, [300, 200], [300, 200, 100]),
+                                "c3": bench_paper_tree(fb, ctx, c3, [150, 100], [150, 100, 64])}
         print(f"[bench] single/decode/full-search done", file=sys.stderr, flush=True)
 
     if not args.no_serving:

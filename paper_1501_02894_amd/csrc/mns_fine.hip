@@ -6,8 +6,8 @@
 // encoder stages, and a 2 x 2 range is half a packed dword wide.  This
 // encoder therefore works on pixels.  One wave owns one top tile: it stages
 // the tile's 2 B_max x 2 B_max domain region (which holds the tile and every
-// descendant's co-centred domain) in LDS and forms each domain mean from its
-// four pixels where it needs it.
+// descendant's co-centred domain) in LDS and forms each range's domain block
+// (the 2 x 2 means, at whichever phase) from those pixels once.
 //
 // Per level (B = B_max >> (l - 1)), a team of T = min(64, B^2) lanes takes
 // one range, B^2 / T pixels per lane: each lane adds r, r^2, d, d^2 and the
@@ -31,6 +31,7 @@ struct FineLds {
   static constexpr int R = 2 * BMAX;                   // staged region side (px)
   static constexpr int MAXE = (BMAX / 2) * (BMAX / 2);  // ranges of one level at most
   uint8_t px[R * R];
+  uint8_t dblk[256];           // domain blocks of the ranges of one pass
   uint16_t list[2][MAXE];      // ranges: lx | ly << 8, pixels inside the tile
   uint32_t fit[MAXE];          // phase-1 fit word per range
   uint32_t mom[MAXE][5];       // identity moments per range (phase 2 of the parents)
@@ -80,33 +81,46 @@ __device__ __forceinline__ int fine_level(FineLds<BMAX>& S, const FineArgs& a, c
   const int W = (int)a.w, H = (int)a.h;
   const bool p2 = level > 1 && a.phase2 != 0;
 
-  // moments and phase-1 fit of every listed range
+  // moments and phase-1 fit of every listed range; each pass first writes
+  // its ranges' B x B domain blocks d (2 x 2 means) to dblk, then reads
+  // them under the eight isometries
+  const bool iso = a.identity_only == 0;
   for (int base = 0; base < nc; base += RP) {
     const int idx = base + lane / T;
     const bool valid = idx < nc;
+    const int db = (lane / T) * N;   // this range's block in dblk
     uint32_t acc[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) acc[j] = 0u;
+    uint32_t rv[PX];
     if (valid) {
       const uint32_t ent = S.list[buf][idx];
       const int x = t.X + (int)(ent & 0xffu), y = t.Y + (int)(ent >> 8);
       const int qx = x - t.rx, qy = y - t.ry;
       const int ox = clampi(x - B / 2, 0, W - 2 * B) - t.rx, oy = clampi(y - B / 2, 0, H - 2 * B) - t.ry;
-      auto dm = [&](int i, int j) -> uint32_t {   // d[i][j]: round-half-up mean of a 2 x 2 group
+#pragma unroll
+      for (int u = 0; u < PX; ++u) {
+        const int q = sub + T * u;
+        const int i = q / B, j = q % B;
         const int o = (oy + 2 * i) * R + ox + 2 * j;
-        return ((uint32_t)S.px[o] + S.px[o + 1] + S.px[o + R] + S.px[o + R + 1] + 2u) >> 2;
-      };
+        const uint32_t d = ((uint32_t)S.px[o] + S.px[o + 1] + S.px[o + R] + S.px[o + R + 1] + 2u) >> 2;
+        S.dblk[db + q] = (uint8_t)d;
+        rv[u] = S.px[(qy + i) * R + qx + j];
+        acc[0] += rv[u];
+        acc[1] += rv[u] * rv[u];
+        acc[2] += d;
+        acc[3] += d * d;
+        acc[4] += rv[u] * d;          // T_0: d[i][j]
+      }
+    }
+    wave_lds_sync();
+    if (valid && iso) {
+      auto dm = [&](int i, int j) -> uint32_t { return S.dblk[db + i * B + j]; };
 #pragma unroll
       for (int u = 0; u < PX; ++u) {
         const int q = sub + T * u;
         const int i = q / B, j = q % B, i2 = B - 1 - i, j2 = B - 1 - j;
-        const uint32_t r = S.px[(qy + i) * R + qx + j];
-        const uint32_t d0 = dm(i, j);
-        acc[0] += r;
-        acc[1] += r * r;
-        acc[2] += d0;
-        acc[3] += d0 * d0;
-        acc[4] += r * d0;             // T_0: d[i][j]
+        const uint32_t r = rv[u];
         acc[5] += r * dm(i, j2);      // T_1: d[i][B-1-j]
         acc[6] += r * dm(i2, j);      // T_2: d[B-1-i][j]
         acc[7] += r * dm(i2, j2);     // T_3: d[B-1-i][B-1-j]
@@ -116,13 +130,16 @@ __device__ __forceinline__ int fine_level(FineLds<BMAX>& S, const FineArgs& a, c
         acc[11] += r * dm(j2, i2);    // T_7: d[B-1-j][B-1-i]
       }
     }
+    wave_lds_sync();   // dblk is rewritten by the next pass
+    // totals over the team: DPP inside rows of 16 lanes, then across rows
+    team_reduce(acc, T < 16 ? T : 16);
 #pragma unroll
-    for (int off = T / 2; off > 0; off >>= 1) {
+    for (int off = 16; off < T; off <<= 1) {
 #pragma unroll
       for (int j = 0; j < 12; ++j) acc[j] += __shfl_xor(acc[j], off);
     }
     if (valid && sub == 0) {
-      if (a.identity_only) {
+      if (!iso) {
 #pragma unroll
         for (int j = 5; j < 12; ++j) acc[j] = acc[4];
       }
@@ -233,7 +250,17 @@ __global__ __launch_bounds__(64 * kFineWaves) void mns_fine_kernel(FineArgs a) {
   t.rx = clampi(t.X - BMAX / 2, 0, W - 2 * BMAX);
   t.ry = clampi(t.Y - BMAX / 2, 0, H - 2 * BMAX);
   t.slot0 = (uint64_t)tile * CELLS;
-  for (int k = lane; k < R * R; k += 64) S.px[k] = a.img[(size_t)(t.ry + k / R) * a.stride + (size_t)(t.rx + k % R)];
+  if constexpr (BMAX >= 8) {
+    // rx is a multiple of 4 (X - BMAX / 2 or W - 2 BMAX), as are the
+    // stride and the image address: whole dwords
+    uint32_t* px4 = reinterpret_cast<uint32_t*>(S.px);
+    for (int k = lane; k < R * R / 4; k += 64) {
+      const int row = k / (R / 4), c4 = k % (R / 4);
+      px4[k] = *reinterpret_cast<const uint32_t*>(a.img + (size_t)(t.ry + row) * a.stride + (size_t)(t.rx + 4 * c4));
+    }
+  } else {
+    for (int k = lane; k < R * R; k += 64) S.px[k] = a.img[(size_t)(t.ry + k / R) * a.stride + (size_t)(t.rx + k % R)];
+  }
   if (lane == 0) S.list[0][0] = 0;
   wave_lds_sync();
   uint64_t mask = 0;
