@@ -146,7 +146,11 @@ def timed_kernel(fb, ctx, slot, fn, reps):
     return (ms[slot] / cnt[slot] if cnt[slot] else float("nan")), cnt[slot] / reps, wall
 
 
-def bench_single(fb, ctx, img, b_max, b_min, thr, reps=10):
+def bench_single(fb, ctx, img, b_max, b_min, thr, reps=10, cold_reps=0):
+    """One image: encode kernel time (HIP events) and call time; with
+    cold_reps, also the kernel time after overwriting 1 GiB of device memory
+    before each call (the image and scratch no longer in L2 / Infinity
+    Cache)."""
     import torch
     t = torch.from_numpy(img).cuda()
     p = fb.make_params(b_max, b_min, thr)
@@ -156,9 +160,25 @@ def bench_single(fb, ctx, img, b_max, b_min, thr, reps=10):
     kms, _, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE, lambda: fb.fe_encode(ctx.handle, t, p, out=out), reps)
     tiles = (img.shape[0] // b_max) * (img.shape[1] // b_max)
     blocks = gpu_range_blocks(out, n, tiles, b_max, b_min)
-    return {"pixels": int(img.size), "records": n, "range_blocks": blocks, "kernel_ms": kms,
-            "call_ms": wall, "range_blocks_per_s": blocks / (wall / 1e3),
-            "kernel_GBps": (img.size + 16 * n + 8 * tiles) / (kms / 1e3) / 1e9}, out[:n]
+    alg = img.size + 16 * n + 8 * tiles
+    res = {"pixels": int(img.size), "records": n, "range_blocks": blocks, "kernel_ms": kms,
+           "call_ms": wall, "range_blocks_per_s": blocks / (wall / 1e3),
+           "kernel_GBps": alg / (kms / 1e3) / 1e9}
+    if cold_reps:
+        junk = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        fb.fe_timing_read(ctx.handle)
+        fb.fe_timing_enable(ctx.handle, True)
+        for _ in range(cold_reps):
+            junk.fill_(1)
+            fb.fe_encode(ctx.handle, t, p, out=out)
+        torch.cuda.synchronize()
+        fb.fe_timing_enable(ctx.handle, False)
+        ms, cnt = fb.fe_timing_read(ctx.handle)
+        cms = ms[fb.FE_TIMING_ENCODE] / max(1, cnt[fb.FE_TIMING_ENCODE])
+        res["cold"] = {"kernel_ms": cms, "kernel_GBps": alg / (cms / 1e3) / 1e9}
+        del junk
+    return res, out[:n]
 
 
 def bench_decode(fb, ctx, recs, w, h, b_max, iters=12, reps=3):
@@ -546,6 +566,17 @@ def main():
     fb.fe_timing_enable(ctx.handle, False)
     fb.fe_timing_select(ctx.handle, 0xffffffff)
     sms, scnt = fb.fe_timing_read(ctx.handle)
+    # the distribution of single steps: 20 more, each between two events on
+    # the stream the library launches on (torch's current stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    st = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    step_dist = {"reps": int(st.size), "median_ms": float(np.median(st)), "p99_ms": float(np.percentile(st, 99)),
+                 "min_ms": float(st.min()), "max_ms": float(st.max())}
 
     off_h = offsets.cpu().numpy()
     n_rec = int(off_h[-1])
@@ -645,6 +676,7 @@ def main():
         "graph": {"ms_per_step": graph_ms, "range_blocks_per_s": blocks / (graph_ms / 1e3),
                   "same_offsets": graph_same},
         "scatter_ms": sc_ms,
+        "step_events": step_dist,
     }
 
     if not args.no_extras:
@@ -664,6 +696,30 @@ def main():
         plain_ms = (time.perf_counter() - tp0) * 1e3 / reps
         result["plain"] = {"ms_per_batch": plain_ms, "images_per_s": len(images) / (plain_ms / 1e3),
                            "range_blocks_per_s": blocks / (plain_ms / 1e3)}
+        # end to end: the batch from pinned host memory (one copy), the
+        # encode, the stream back to pinned host memory
+        host_in = torch.empty(int(offs[-1]), dtype=torch.uint8).pin_memory()
+        host_in.copy_(torch.from_numpy(np.concatenate([im.reshape(-1) for im in images])))
+        host_out = torch.empty((n_rec, 16), dtype=torch.uint8).pin_memory()
+
+        def e2e():
+            flat.copy_(host_in, non_blocking=True)
+            step()
+            host_out.copy_(out[:n_rec], non_blocking=True)
+
+        e2e()
+        torch.cuda.synchronize()
+        te0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            e2e()
+        torch.cuda.synchronize()
+        e2e_ms = (time.perf_counter() - te0) * 1e3 / reps
+        result["end_to_end"] = {"ms_per_batch": e2e_ms, "images_per_s": len(images) / (e2e_ms / 1e3),
+                                "range_blocks_per_s": blocks / (e2e_ms / 1e3),
+                                "bytes_h2d": int(offs[-1]), "bytes_d2h": 16 * n_rec,
+                                "same_stream": bool(torch.equal(host_out, out[:n_rec].cpu()))}
+        del host_in, host_out
         # cold Infinity Cache: overwrite 1 GiB before each timed launch
         junk = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         fb.fe_timing_enable(ctx.handle, True)
@@ -682,7 +738,7 @@ def main():
         from paper_1501_02894_amd import synth
         c2, c3 = pooled(_gen_named, ["c2", "c3"], 2)
         res_c2, _ = bench_single(fb, ctx, c2, 16, 4, [300, 200])
-        res_c3, recs_c3 = bench_single(fb, ctx, c3, 32, 4, [150, 100, 64], reps=5)
+        res_c3, recs_c3 = bench_single(fb, ctx, c3, 32, 4, [150, 100, 64], reps=5, cold_reps=5)
         res_dec, _ = bench_decode(fb, ctx, recs_c3, 4096, 4096, 32)
         res_fs = bench_fullsearch(fb, ctx, c2, 16, 4, [300, 200])
         result["c2_single"] = res_c2
