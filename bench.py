@@ -113,6 +113,28 @@ def cpu_baseline(images, budget_s: float):
     return blocks / dt, used, recs, dt
 
 
+def cpu_fullsearch_sample(img, B=16, n=16, seed=2):
+    """The exhaustive-search oracle on a seeded sample of n level-1 ranges
+    of one image, its BLAS on the host cores of one GPU's share (at most
+    16); ranges/s."""
+    from oracle import fullsearch
+    from threadpoolctl import threadpool_limits
+    H, W = img.shape
+    rng = np.random.default_rng(seed)
+    pick = rng.choice((H // B) * (W // B), size=n, replace=False)
+    xs = (pick % (W // B)) * B
+    ys = (pick // (W // B)) * B
+    cores = min(16, len(os.sched_getaffinity(0)))
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        fullsearch.best_matches(img, xs, ys, B)
+        dt = time.perf_counter() - t0
+    ndom = (W - 2 * B + 1) * (H - 2 * B + 1)
+    return {"value": n / dt, "unit": "ranges/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded level-1 ranges (B={B}) of C2 against all {ndom} step-1 domains and "
+                      f"8 isometries, fp64 BLAS, {dt:.1f} s"}
+
+
 def pooled(fn, args, workers=8):
     from concurrent.futures import ProcessPoolExecutor
     with ProcessPoolExecutor(min(workers, os.cpu_count() or 1)) as ex:
@@ -776,6 +798,9 @@ def main():
                                             f"({sum(images[k].size for k in used)} px), {dt:.1f} s, "
                                             f"numpy int64, one thread"}
         result["bit_exact"] = {"checked_images": len(used), "equal": parity}
+        if not args.no_extras:
+            from paper_1501_02894_amd import synth
+            result["cpu_baseline"]["fullsearch"] = cpu_fullsearch_sample(synth.workload("c2"))
     print(json.dumps(result), flush=True)
 
 
