@@ -127,9 +127,9 @@ typedef struct fe_transform {
  *   b_max, b_min  largest and smallest range side: powers of two with
  *                 2 <= b_min <= b_max, 4 <= b_max <= 32 and at most four
  *                 levels (two level bits, Sec. 3.3; the paper's tree is
- *                 16 -> 2).  b_min = 2 is taken by fe_encode only (MNS or
- *                 no-search, b_max 4, 8 or 16; not the batch, plan, server,
- *                 exhaustive or local-search paths).
+ *                 16 -> 2).  b_min = 2 is taken by fe_encode and
+ *                 fe_encode_batch (MNS or no-search, b_max 4, 8 or 16), not
+ *                 by plans, the server or the exhaustive and local searches.
  *   n_thr         number of thresholds = L - 1, L = log2(b_max/b_min) + 1.
  *   flags         FE_PHASE2, FE_FULL_SEARCH, FE_IDENTITY_ONLY (MNS only),
  *                 FE_LOCAL_SEARCH (not with FE_FULL_SEARCH).
@@ -220,8 +220,9 @@ fe_status fe_range_moments(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, ui
  * with FE_FULL_SEARCH).  d_img is W x H uint8 with row pitch `stride`
  * bytes (4-byte aligned).  Writes the stream to d_out[0 .. *n_out).
  * With b_min = 2 the 2 x 2 ranges take their co-centred domains at odd
- * origins (x - 1); a separate encoder (one wave per top tile, domain means
- * formed from pixels) runs that tree, with the same stream format.
+ * origins (x - 1): the tree runs down to 4 x 4 as usual, and the 2 x 2
+ * level follows in a second kernel that forms those domains' means from the
+ * pixels; same stream format.
  * Waits for the stream to finish (the count is needed on the host).
  * FE_ERR_CAPACITY if cap is smaller than the stream; *n_out then holds
  * the needed count and d_out is left unspecified.  cap =

@@ -68,6 +68,10 @@ struct fe_ctx {
   size_t pack_chunk_n = 0;
   uint4* zoom_recs = nullptr;         // zoom decoding: the scaled transforms
   size_t zoom_recs_n = 0;
+  uint4* fine_list = nullptr;         // b_min = 2: the 4 x 4 ranges that go on to 2 x 2
+  size_t fine_list_n = 0;
+  uint32_t* fine_count = nullptr;
+  size_t fine_count_n = 0;
   bool last_decode_tiled = false;     // which decoder the last fe_decode ran
   int decode_mode = FE_DECODE_AUTO;
   fe::TileShape shape_override[33][5] = {};
@@ -236,7 +240,6 @@ fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_par
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
   if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) return fe::fail(FE_ERR_INVALID, "batch encode runs MNS only");
-  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "b_min 2 is encoded by fe_encode only");
   if ((uintptr_t)d_out & 15) return fe::fail(FE_ERR_INVALID, "output must be 16-byte aligned");
   for (uint32_t k = 0; k < n_imgs; ++k) {
     if (!h_imgs[k].data || h_imgs[k].reserved) return fe::fail(FE_ERR_INVALID, "image %u: bad descriptor", k);
@@ -277,11 +280,18 @@ fe_status build_table(const fe_image_desc* imgs, uint32_t n_imgs, const fe_param
 // Shared MNS encode of a list of images with common parameters.
 fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
                         fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
-  const int L = fe::levels_of(p->b_max, p->b_min);
+  // b_min = 2: the fused kernel runs the tree down to 4 x 4 (its EXT form,
+  // default tile shape) and the 2 x 2 level follows in a kernel of its own
+  const bool ext = p->b_min < 4;
+  const int L = fe::levels_of(p->b_max, ext ? 4u : p->b_min);   // fused levels
   const int bmax = (int)p->b_max;
-  const fe::TileShape shape = pick_shape(ctx, bmax, L);
+  fe::TileShape shape = pick_shape(ctx, bmax, L);
+  if (ext) {
+    fe::TileShape first[16];
+    shape = fe::encode_shapes(bmax, L, first, 16) > 0 ? first[0] : fe::TileShape{0, 0};
+  }
   if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
-  const int cells = 1 << (2 * (L - 1));
+  const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));
   std::vector<fe::ImgDev> table;
   uint64_t tiles = 0;
   uint32_t wgs = 0;
@@ -302,6 +312,11 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   if (!offsets) {
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
     offsets = ctx->offsets;
+  }
+  const uint64_t fine_max = ext ? tiles * (uint64_t)(bmax / 4) * (uint64_t)(bmax / 4) : 0;
+  if (ext) {
+    if ((st = ensure(ctx->fine_list, ctx->fine_list_n, (size_t)fine_max, "4 x 4 range list")) != FE_OK) return st;
+    if ((st = ensure(ctx->fine_count, ctx->fine_count_n, 1, "4 x 4 range count")) != FE_OK) return st;
   }
   if ((st = upload_table(ctx, table.data(), n_imgs, tiles, s)) != FE_OK) return st;
 
@@ -332,9 +347,31 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
   a.staging = ctx->staging;
   a.masks = ctx->masks;
+  if (ext) {
+    a.fine_list = ctx->fine_list;
+    a.fine_count = ctx->fine_count;
+    FE_HIP(fe::launch_zero_u32(ctx->fine_count, 1, s), "zero 4 x 4 count");
+  }
   {
     Timed t(ctx, FE_TIMING_ENCODE, s);
-    FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
+    if (!ext) {
+      FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
+    } else {
+      FE_HIP(fe::launch_mns_tiles_ext(bmax, L, shape, a, s), "encode kernel launch");
+      fe::FinishArgs f{};
+      f.imgs = ctx->d_table;
+      f.n_imgs = n_imgs;
+      f.list = ctx->fine_list;
+      f.count = ctx->fine_count;
+      f.gx = (uint32_t)shape.gx;
+      f.level = (uint32_t)L;
+      f.thr = p->mse_thr[L - 1];
+      f.phase2 = a.phase2;
+      f.identity_only = a.identity_only;
+      f.staging = ctx->staging;
+      f.masks = ctx->masks;
+      FE_HIP(fe::launch_fine_finish(f, fine_max, s), "2 x 2 level launch");
+    }
   }
   {
     Timed t(ctx, FE_TIMING_SCATTER, s);
@@ -453,64 +490,6 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
   return FE_OK;
 }
 
-// MNS quadtree down to 2 x 2 ranges (b_min = 2) of one image: one launch
-// over the top tiles, then the ordering kernels over one-tile blocks.
-fe_status encode_fine(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, uint32_t stride, const fe_params* p,
-                      fe_transform* d_out, size_t cap, size_t* n_out, hipStream_t s) {
-  if (p->b_max > 16)
-    return fe::fail(FE_ERR_INVALID, "b_min 2 needs b_max <= 16 (got %u)", p->b_max);
-  const int L = fe::levels_of(p->b_max, p->b_min);
-  const int cells = 1 << (2 * (L - 1));
-  const uint64_t tiles = (uint64_t)(w / p->b_max) * (h / p->b_max);
-  fe_status st;
-  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
-  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
-  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
-  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
-  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
-  if ((st = ensure(ctx->offsets, ctx->offsets_n, 2, "offsets")) != FE_OK) return st;
-  fe::ImgDev im{};
-  im.data = d_img;
-  im.width = w;
-  im.height = h;
-  im.stride = stride;
-  im.tiles_x = w / p->b_max;
-  im.tiles_y = h / p->b_max;
-  im.groups_x = im.tiles_x;
-  im.groups_y = im.tiles_y;
-  im.wg_first = 0;
-  im.tile_first = 0;
-  if ((st = upload_table(ctx, &im, 1, tiles, s)) != FE_OK) return st;
-  fe::FineArgs a{};
-  a.img = d_img;
-  a.w = w;
-  a.h = h;
-  a.stride = stride;
-  a.tiles_x = w / p->b_max;
-  a.tiles = (uint32_t)tiles;
-  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
-  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
-  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
-  a.staging = ctx->staging;
-  a.masks = ctx->masks;
-  {
-    Timed t(ctx, FE_TIMING_ENCODE, s);
-    FE_HIP(fe::launch_mns_fine((int)p->b_max, a, s), "encode kernel launch");
-  }
-  {
-    Timed t(ctx, FE_TIMING_SCATTER, s);
-    FE_HIP(fe::launch_scatter(ctx->d_table, 1, nullptr, tiles, cells, fe::TileShape{1, 1}, ctx->masks,
-                              ctx->chunk_sum, ctx->chunk_base, ctx->staging, reinterpret_cast<uint4*>(d_out),
-                              (uint64_t)cap, ctx->offsets, s),
-           "scatter launch");
-  }
-  FE_HIP(hipMemcpyAsync(ctx->h_scalars, ctx->offsets + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "count");
-  FE_HIP(hipStreamSynchronize(s), "encode");
-  *n_out = (size_t)ctx->h_scalars[0];
-  if (*n_out > cap) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
-  return FE_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -574,6 +553,8 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->dec_pieces);
   (void)hipFree(c->pack_chunk);
   (void)hipFree(c->zoom_recs);
+  (void)hipFree(c->fine_list);
+  (void)hipFree(c->fine_count);
   if (c->ev) {
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
       if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -622,7 +603,6 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint32_t h, u
     if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "the exhaustive and local searches need b_min >= 4");
     return encode_full_search(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
   }
-  if (p->b_min < 4) return encode_fine(ctx, d_img, w, h, stride, p, d_out, cap, n_out, (hipStream_t)stream);
   fe_image_desc one{d_img, w, h, stride, 0};
   return encode_images(ctx, &one, 1, p, d_out, cap, nullptr, n_out, (hipStream_t)stream);
 }
@@ -1015,6 +995,7 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   *out = nullptr;
   fe_status st = check_batch(h_imgs, n_imgs, p, d_out, d_offsets);
   if (st != FE_OK) return st;
+  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "a plan records trees that stop at 4 x 4 (b_min >= 4)");
   DeviceGuard g(ctx->device);
   const int L = fe::levels_of(p->b_max, p->b_min);
   const int bmax = (int)p->b_max;

@@ -45,6 +45,13 @@ struct EncodeArgs {
   // (cell 0) lie side by side.
   uint4* staging;
   uint64_t* masks;     // per tile: bit c set when cell c holds a record
+  // Trees that reach 2 x 2 ranges (the kernel's EXT form): the 4 x 4 level
+  // is tested against thr[L-1] instead of being stored, record cells are
+  // 2 x 2 units, and each failed 4 x 4 range is appended to fine_list
+  // (count in *fine_count) for the 2 x 2 level: x | y << 16, the record
+  // slot of its first child, its tile's global index, m | cell << 8.
+  uint4* fine_list;
+  uint32_t* fine_count;
 };
 
 constexpr int kChunkTiles = 256;  // tiles per scatter workgroup
@@ -61,6 +68,10 @@ int encode_shapes(int b_max, int levels, TileShape* out, int max_out);
 // hipErrorInvalidValue when the combination is not instantiated.
 hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const EncodeArgs& args,
                             hipStream_t stream);
+// The EXT form for trees that continue to 2 x 2 (levels = the fused levels,
+// b_max -> 4; default tile shape only).
+hipError_t launch_mns_tiles_ext(int b_max, int levels, TileShape shape, const EncodeArgs& args,
+                                hipStream_t stream);
 
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
 
@@ -97,19 +108,22 @@ struct DecodeArgs {
   uint32_t width, height, b_max, pad;
 };
 hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t stream);
-// Encoder of quadtrees that reach 2 x 2 ranges (b_min = 2, b_max 4, 8 or
-// 16): one wave per top tile of one image; records go to staging[tile *
-// cells + Morton cell of 2 x 2 units], the tile's occupancy to masks[tile].
-struct FineArgs {
-  const uint8_t* img;
-  uint32_t w, h, stride;
-  uint32_t tiles_x, tiles;
+// The 2 x 2 level of trees that reach 2 x 2 ranges: for each 4 x 4 range
+// the fused kernel listed (EXT form), phase 2 over its four 2 x 2 children
+// and, where that fails, the children's phase-1 records (the last level).
+struct FinishArgs {
+  const ImgDev* imgs;
+  uint32_t n_imgs;
+  const uint4* list;
+  const uint32_t* count;
+  uint32_t gx;          // record-slot stride between a range's children
+  uint32_t level;       // 1-based level of the listed 4 x 4 ranges
+  uint32_t thr;         // their MSE threshold (phase 2)
   uint32_t phase2, identity_only;
-  uint32_t thr[4];
   uint4* staging;
   uint64_t* masks;
 };
-hipError_t launch_mns_fine(int b_max, const FineArgs& a, hipStream_t stream);
+hipError_t launch_fine_finish(const FinishArgs& a, uint64_t max_entries, hipStream_t stream);
 
 // Native check of a.recs (count into *bad) and the records zoomed by z into out.
 hipError_t launch_decode_zoom(const DecodeArgs& a, uint32_t z, uint4* out, uint32_t* bad, hipStream_t stream);

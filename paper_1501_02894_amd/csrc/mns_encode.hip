@@ -277,9 +277,13 @@ __device__ __forceinline__ uint32_t rec_slot(uint32_t t, int cell, int cells) {
   return (t / GX) * (uint32_t)(GX * cells) + (uint32_t)cell * GX + t % GX;
 }
 
-template <int BMAX, int L, int GX, int GY>
+template <int BMAX, int L, int GX, int GY, bool EXT>
 __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm) {
   using G = Geo<BMAX, L, GX, GY>;
+  // record cells per tile: B_min cells, or 2 x 2 cells when the tree goes on
+  // to 2 x 2 (EXT), whose Morton codes are those of the B_min cells times 4
+  constexpr int CE = EXT ? 4 * G::CELLS : G::CELLS;
+  constexpr int CSH = EXT ? 2 : 0;
   const Region& rg = bg.rg;
   const int gx = bg.gx, gy = bg.gy;
   const int tid = threadIdx.x;
@@ -287,7 +291,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   const uint32_t* s_h0 = sm.h0;
   const uint32_t* s_h0t = sm.h0t;
   unsigned long long* s_mask = sm.mask;
-  const uint64_t slot0 = (uint64_t)bg.sblk * (uint64_t)(G::NT * G::CELLS);   // the block's record slots
+  const uint64_t slot0 = (uint64_t)bg.sblk * (uint64_t)(G::NT * CE);   // the block's record slots
   const int wave = tid >> 6, lane = tid & 63;
   const int t_first = wave * G::NTW;
   uint32_t* w_meta0 = sm.meta[wave][0];
@@ -308,7 +312,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
     uint32_t* nxt = (lev & 1) ? w_meta1 : w_meta0;
     const uint32_t* ppar = sm.par[wave][(lev - 1) & 1];   // parents of `cur` (level lev-1)
     uint32_t* npar = sm.par[wave][lev & 1];               // parents of `nxt`
-    const bool last = lev == L;
+    const bool last = lev == L && !EXT;   // EXT: the 4 x 4 level is tested too
     const uint32_t thr = last ? 0u : a.thr[lev - 1];
     const int B = BMAX >> (lev - 1);
     uint32_t nfail = 0;
@@ -386,8 +390,8 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
               constexpr int PB = 2 * BB;
               const int pdx = clampi(PX - PB / 2, 0, rg.W - 2 * PB);
               const int pdy = clampi(PY - PB / 2, 0, rg.H - 2 * PB);
-              const int cell = morton(pmeta);
-              a.staging[slot0 + rec_slot<GX>((pmeta >> 16) & 0xffu, cell, G::CELLS)] =
+              const int cell = morton(pmeta) << CSH;
+              a.staging[slot0 + rec_slot<GX>((pmeta >> 16) & 0xffu, cell, CE)] =
                   make_record(PX, PY, pdx, pdy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
               atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
             }
@@ -401,8 +405,8 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
           if (fit & kFitAccept) {
             const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
             const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
-            const int cell = morton(meta);
-            a.staging[slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, G::CELLS)] =
+            const int cell = morton(meta) << CSH;
+            a.staging[slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, CE)] =
                 make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                             (int)(fit & 0xffu), 0, 0, 0);
             atomicOr(&s_mask[meta >> 16], 1ull << cell);
@@ -411,6 +415,28 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
           }
         }
         const uint64_t bal = __ballot(fail);
+        if constexpr (EXT) {
+          if (lev == L) {
+            // failed 4 x 4 ranges go on to the 2 x 2 level, through the
+            // global list (one atomic per wave)
+            if (bal) {
+              const int first = (int)__builtin_ctzll(bal);
+              uint32_t base = 0;
+              if (lane == first) base = atomicAdd(a.fine_count, (uint32_t)__popcll(bal));
+              base = (uint32_t)__shfl((int)base, first);
+              if (fail) {
+                const uint32_t q = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                const int cell = morton(meta) << CSH;
+                a.fine_list[q] = make_uint4((uint32_t)X | ((uint32_t)Y << 16),
+                                            (uint32_t)(slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, CE)),
+                                            (uint32_t)tile_global<G::LOG_GX>(meta, rg),
+                                            (fit & 0xffu) | ((uint32_t)cell << 8));
+              }
+            }
+            continue;
+          }
+        }
         if (fail) {
           const uint32_t q = nfail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -438,7 +464,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   if (my_valid) a.masks[tile_global<G::LOG_GX>((uint32_t)my_t << 16, rg)] = s_mask[my_t];
 }
 
-template <int BMAX, int L, int GX, int GY>
+template <int BMAX, int L, int GX, int GY, bool EXT>
 __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   using G = Geo<BMAX, L, GX, GY>;
   __shared__ Lds<BMAX, L, GX, GY> sm;
@@ -451,7 +477,7 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   Stage<G>::run(bg, tid, sm.img, sm.h0, sm.h0t);
   for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
   __syncthreads();
-  process_block<BMAX, L, GX, GY>(a, bg, sm);
+  process_block<BMAX, L, GX, GY, EXT>(a, bg, sm);
 }
 
 // One lane per logical workgroup: find its image (binary search over the
@@ -482,10 +508,10 @@ __global__ __launch_bounds__(256) void block_prep_kernel(const ImgDev* imgs, uin
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-template <int BMAX, int L, int GX, int GY>
+template <int BMAX, int L, int GX, int GY, bool EXT = false>
 static hipError_t launch_one(const EncodeArgs& a, hipStream_t s) {
   const uint32_t grid = ((a.n_wg + 7u) >> 3) << 3;
-  hipLaunchKernelGGL((mns_tiles_kernel<BMAX, L, GX, GY>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((mns_tiles_kernel<BMAX, L, GX, GY, EXT>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -514,6 +540,14 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
   if (b_max == BM && levels == LV && shape.gx == GX_ && shape.gy == GY_) return launch_one<BM, LV, GX_, GY_>(a, s);
   FE_SHAPES(FE_LAUNCH)
 #undef FE_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mns_tiles_ext(int b_max, int levels, TileShape shape, const EncodeArgs& a, hipStream_t s) {
+  // the default shapes of 16 -> 4, 8 -> 4 and 4 -> 4
+  if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 8) return launch_one<16, 3, 8, 8, true>(a, s);
+  if (b_max == 8 && levels == 2 && shape.gx == 8 && shape.gy == 8) return launch_one<8, 2, 8, 8, true>(a, s);
+  if (b_max == 4 && levels == 1 && shape.gx == 16 && shape.gy == 16) return launch_one<4, 1, 16, 16, true>(a, s);
   return hipErrorInvalidValue;
 }
 

@@ -1,8 +1,9 @@
 """GPU parity of quadtrees that reach the paper's 2 x 2 ranges (Sec. 3.3:
 four levels, 16 x 16 to 2 x 2), through the C ABI.
 
-The encoder for b_min = 2 (one wave per top tile, domain means formed from
-pixels at either phase) must give the oracle's stream byte for byte; both
+The encoder for b_min = 2 (the fused kernel down to 4 x 4, then the 2 x 2
+level with domain means formed from pixels at either phase) must give the
+oracle's stream byte for byte, alone and in a batch; both
 decoders, zoom decoding and the compressed file must take such streams (the
 tile decoder steps aside for blocks under 4 x 4, and takes them again once a
 zoom has made them 4 x 4 or larger)."""
@@ -156,6 +157,20 @@ def test_pack(torch_dev, ctx, iso):
     assert back.tobytes() == np.ascontiguousarray(rec).tobytes()
 
 
+@pytest.mark.parametrize("b_max,thr", [(16, [300, 200, 100]), (8, [300, 150])])
+def test_batch(torch_dev, ctx, b_max, thr):
+    # images of several sizes in one launch; each stream equals the oracle's
+    log(f"fine batch b{b_max}")
+    imgs = [synth.workload("c1"), synth.noise_1f(48, 80, 61), synth.piecewise_smooth(96, 64, 62, cells=12),
+            synth.noise_1f(32, 32, 63), synth.workload("c2")]
+    views = [dev(torch_dev, im) for im in imgs]
+    out, offs, n = ctx.encode_batch(views, b_max, 2, thr)
+    offs = offs.cpu().numpy()
+    got = fb.to_records(out[:n])
+    for k, im in enumerate(imgs):
+        assert_same_stream(got[offs[k]:offs[k + 1]], mns.encode(im, b_max, 2, thr))
+
+
 def test_paths_that_do_not_take_2x2(torch_dev, ctx):
     log("fine rejections")
     img = dev(torch_dev, synth.workload("c1"))
@@ -163,7 +178,9 @@ def test_paths_that_do_not_take_2x2(torch_dev, ctx):
         ctx.encode(img, 8, 2, [300, 150], full_search=True)
     with pytest.raises(fb.FeError):
         ctx.encode(img, 8, 2, [300, 150], local_search=True)
+    out = torch_dev.empty((fb.fe_max_transforms(64, 64, 2), 16), dtype=torch_dev.uint8, device="cuda")
+    offs = torch_dev.zeros(2, dtype=torch_dev.int64, device="cuda")
     with pytest.raises(fb.FeError):
-        ctx.encode_batch([img, img], 8, 2, [300, 150])
+        fb.Plan(ctx, [img], 8, 2, [300, 150], out, offs)
     with pytest.raises(fb.FeError):
         ctx.encode(img, 32, 2, [1, 1, 1, 1])        # five levels
