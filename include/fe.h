@@ -392,8 +392,11 @@ fe_status fe_full_search_ranges(fe_ctx* ctx, const uint8_t* d_img, uint32_t widt
  * around the block.  fe_tile_shapes lists the shapes built for (b_max,
  * b_min) (first = default) and returns their number (at most max_out
  * written).  fe_set_tile_shape selects one for a context (gx = gy = 0
- * restores the default); FE_ERR_INVALID if the shape is not built.  The
- * encoded stream does not depend on the shape.
+ * restores the default); FE_ERR_INVALID if the shape is not built.  With
+ * no shape set, an encode call whose tiles would fill fewer than 256
+ * default-shape workgroups (one per compute unit) takes the shape with the
+ * fewest tiles per workgroup.  The encoded stream does not depend on the
+ * shape.
  */
 int fe_tile_shapes(uint32_t b_max, uint32_t b_min, uint32_t* gx, uint32_t* gy, int max_out);
 fe_status fe_set_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_t gx, uint32_t gy);

@@ -166,6 +166,10 @@ struct Timed {
   }
 };
 
+// Calls whose tiles fill fewer default-shape workgroups than this (the
+// chip's compute units) use the smallest shape instead.
+constexpr uint64_t kSmallCallGroups = 256;
+
 fe::TileShape pick_shape(fe_ctx* ctx, int b_max, int L) {
   fe::TileShape o = ctx->shape_override[b_max][L];
   if (o.gx > 0) return o;
@@ -289,6 +293,23 @@ fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs,
   if (ext) {
     fe::TileShape first[16];
     shape = fe::encode_shapes(bmax, L, first, 16) > 0 ? first[0] : fe::TileShape{0, 0};
+  }
+  if (ext || ctx->shape_override[bmax][L].gx <= 0) {
+    // a call too small to give the default shape a workgroup per CU (a
+    // single 512 x 512 image, say) takes the shape with the fewest tiles
+    // per workgroup: more, shorter workgroups
+    uint64_t all_tiles = 0;
+    for (uint32_t k = 0; k < n_imgs; ++k) all_tiles += (uint64_t)(imgs[k].width / p->b_max) * (imgs[k].height / p->b_max);
+    fe::TileShape cand[16];
+    const int k = fe::encode_shapes(bmax, L, cand, 16);
+    if (k > 0 && all_tiles / (uint64_t)(cand[0].gx * cand[0].gy) < kSmallCallGroups) {
+      shape = cand[0];
+      for (int i = 1; i < k; ++i)
+        if (cand[i].gx * cand[i].gy < shape.gx * shape.gy) shape = cand[i];
+      // the EXT form is built for (16, 3, 4 x 2) and (8, 2, 4 x 4) besides the defaults
+      if (ext && !((bmax == 16 && shape.gx == 4 && shape.gy == 2) || (bmax == 8 && shape.gx == 4 && shape.gy == 4)))
+        shape = cand[0];
+    }
   }
   if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
   const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));

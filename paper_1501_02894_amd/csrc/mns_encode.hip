@@ -544,9 +544,12 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
 }
 
 hipError_t launch_mns_tiles_ext(int b_max, int levels, TileShape shape, const EncodeArgs& a, hipStream_t s) {
-  // the default shapes of 16 -> 4, 8 -> 4 and 4 -> 4
+  // the default shapes of 16 -> 4, 8 -> 4 and 4 -> 4, and the smallest of
+  // the first two (for calls with few tiles)
   if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 8) return launch_one<16, 3, 8, 8, true>(a, s);
+  if (b_max == 16 && levels == 3 && shape.gx == 4 && shape.gy == 2) return launch_one<16, 3, 4, 2, true>(a, s);
   if (b_max == 8 && levels == 2 && shape.gx == 8 && shape.gy == 8) return launch_one<8, 2, 8, 8, true>(a, s);
+  if (b_max == 8 && levels == 2 && shape.gx == 4 && shape.gy == 4) return launch_one<8, 2, 4, 4, true>(a, s);
   if (b_max == 4 && levels == 1 && shape.gx == 16 && shape.gy == 16) return launch_one<4, 1, 16, 16, true>(a, s);
   return hipErrorInvalidValue;
 }

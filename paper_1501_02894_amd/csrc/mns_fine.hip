@@ -15,8 +15,8 @@
 // Technique 1 for the parent (Sec. 3.1-3.3) with the level's contrast set
 // and eq. (1); if it holds, the first lane stores the parent's phase-2
 // record in the parent's first cell, otherwise every lane stores its child.
-// Occupancy bits go to the tile masks with 64-bit atomic ORs (the fused
-// encoder has already written its own bits).
+// Occupancy bits go to the tile masks with one 64-bit atomic OR per range
+// (the fused encoder has already written its own bits).
 #include "fe_device.h"
 #include "fe_internal.h"
 
@@ -101,19 +101,18 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
       }
       dead = fit_phase2<2>(mom, m, (int)a.level, a.thr, O, bits);
     }
-    unsigned long long* mask = reinterpret_cast<unsigned long long*>(a.masks + tile);
     if (dead) {
-      if (c == 0) {
+      if (c == 0)
         a.staging[ent.y] = make_record(px, py, clampi(px - 2, 0, W - 8), clampi(py - 2, 0, H - 8), (int)a.level - 1,
                                        1, 0, (int)bits, m, O[0] - m, O[1] - m, O[2] - m);
-        atomicOr(mask, 1ull << cell0);
-      }
     } else {
       a.staging[(uint64_t)ent.y + (uint64_t)c * a.gx] =
           make_record(cx, cy, ox, oy, (int)a.level, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                       (int)(fit & 0xffu), 0, 0, 0);
-      atomicOr(mask, 1ull << (cell0 + c));
     }
+    // the parent's cell alone, or its four children's: one atomic per range
+    if (c == 0)
+      atomicOr(reinterpret_cast<unsigned long long*>(a.masks + tile), (dead ? 1ull : 0xfull) << cell0);
   }
 }
 
