@@ -157,11 +157,6 @@ __global__ __launch_bounds__(256) void fs_build_a_kernel(const uint8_t* img, uin
   for (int b = 0; b < BYTES; ++b) dst[b] = out[b];
 }
 
-__global__ void fs_init_best_kernel(uint64_t* best, uint32_t R) {
-  const uint32_t r = blockIdx.x * 256 + threadIdx.x;
-  if (r < R) best[r] = ((uint64_t)kFBias << kIdxBits);   // f = 0 at domain 0, isometry 0
-}
-
 // ------------------------------------------------------------------ GEMM
 // Workgroup: 4 waves x NF A fragments (32 rows = 4 ranges each) against
 // kStripsPerBlock domain rows of 32 domains of one parity class.
@@ -203,7 +198,8 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
       const uint8_t* s = plane + (size_t)row * g.pitch + x0 + 4 * c4;
       v = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16) | ((uint32_t)s[3] << 24);
     }
-    s_pl[r * (C::LP / 4) + c4] = v;
+    // staged centred: d - 128 == d ^ 0x80 as int8
+    s_pl[r * (C::LP / 4) + c4] = v ^ 0x80808080u;
   }
   __syncthreads();
 
@@ -239,7 +235,11 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
     al[k] = rv[k] ? alpha[r] : 0.0;
     be[k] = rv[k] ? beta[r] : 0.0;
     bk[k] = ((uint64_t)kFBias << kIdxBits);
-    thr[k] = 0.0;
+    // screen against the best candidate other workgroups have published so
+    // far: it is a real candidate, so a pair whose bound is strictly worse
+    // cannot win, and ties still pass the screen
+    const int64_t fs = rv[k] ? (int64_t)(best[r] >> kIdxBits) - kFBias : 0;
+    thr[k] = fs < 0 ? -(double)fs : 0.0;
   }
   const double n = (double)(B * B);
   const uint32_t xcol = x0 + (uint32_t)col;
@@ -296,11 +296,6 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
           if (h == 0) bfr.x = val; else bfr.y = val;
         }
       }
-      // centre the domain bytes: d - 128 == d ^ 0x80 as int8
-      bfr.x ^= (int)0x80808080u;
-      bfr.y ^= (int)0x80808080u;
-      bfr.z ^= (int)0x80808080u;
-      bfr.w ^= (int)0x80808080u;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         if constexpr (B == 4) {
@@ -595,8 +590,12 @@ static hipError_t fs_search_t(const FsPlan& pl, const uint8_t* img, uint32_t w, 
                      nfrag, frag);
   hipLaunchKernelGGL(fs_range_sums_kernel, dim3((R + 255) / 256), dim3(256), 0, s, img, stride, (uint32_t)B, xy, R,
                      sr, alpha, beta);
-  hipLaunchKernelGGL(fs_init_best_kernel, dim3((R + 255) / 256), dim3(256), 0, s, best, R);
+  // seed each range's best with its local-search result (the surrounding
+  // step-1 domains, identity only): a real candidate whose key the search
+  // below either improves or reproduces for that domain, so the minimum is
+  // unchanged, while the search's screen starts from a tight threshold
   const FsGeo g = geo_of(pl, w, h, planes);
+  hipLaunchKernelGGL(ls_search_kernel<B>, dim3((R + 3) / 4), dim3(256), 0, s, g, img, stride, sd, qd, xy, R, best);
   const uint32_t maxcols = (pl.nu + 1) / 2, maxrows = (pl.nv + 1) / 2;
   const uint32_t xblocks = (maxcols + 31) / 32, tblocks = (maxrows + kStripsPerBlock - 1) / kStripsPerBlock;
   const uint32_t rgroups = (nfrag + 4 * NF - 1) / (4 * NF);
