@@ -418,7 +418,7 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
   if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) return fe::fail(FE_ERR_INVALID, "the server runs MNS only");
-  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "b_min 2 is encoded by fe_encode only");
+  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "the server serves trees that stop at 4 x 4 (b_min >= 4)");
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
     return fe::fail(FE_ERR_DEVICE, "no HIP device %d", device);
