@@ -1,0 +1,92 @@
+"""The batched workload at its full size, in the launch configuration the
+benchmark times: 256 images (sides 128..2048, 1/f noise and
+piecewise-smooth, 223 M pixels), MNS 16 -> 8 -> 4, thresholds 300, 200, one
+fe_encode_batch over views of one device buffer.
+
+Every image's stream is checked for what holds at any size: records inside
+the image, fields in range, co-centred domains, and blocks that tile the
+image exactly once in stream order (strictly increasing depth-first
+positions whose spans add up to the image).  A seeded sample of images,
+the largest and the smallest among them, is compared with the oracle byte
+for byte."""
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+from oracle import mns
+from paper_1501_02894_amd import binding as fb
+
+pytestmark = pytest.mark.gpu
+
+B_MAX, B_MIN, THR = 16, 4, [300, 200]
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = fb.Context(0)
+    yield c
+    c.close()
+
+
+def _check_structure(r, W, H):
+    L = mns.num_levels(B_MAX, B_MIN)
+    x, y = r["x"].astype(np.int64), r["y"].astype(np.int64)
+    lvl = r["level"].astype(np.int64)
+    assert np.all(lvl < L)
+    B = B_MAX >> lvl
+    assert np.all(x % B == 0) and np.all(y % B == 0)
+    assert np.all(x + B <= W) and np.all(y + B <= H)
+    assert np.array_equal(r["dx"].astype(np.int64), np.clip(x - B // 2, 0, W - 2 * B))
+    assert np.array_equal(r["dy"].astype(np.int64), np.clip(y - B // 2, 0, H - 2 * B))
+    p2 = (r["flags"] & 1) == 1
+    assert np.all(r["flags"] <= 1)
+    assert np.all(r["s_idx"][~p2] < 8) and np.all(r["iso"][~p2] < 8) and np.all(r["iso"][p2] == 0)
+    assert np.all(lvl[p2] < L - 1)
+    assert np.all(r["dlum"][~p2] == 0)
+    # exact tiling: depth-first positions strictly increase and the spans fill every tile
+    key = mns.stream_key(x, y, W, B_MAX, B_MIN)
+    span = (B // B_MIN) ** 2
+    assert np.all(key[1:] >= key[:-1] + span[:-1])
+    assert int(span.sum()) == (W // B_MIN) * (H // B_MIN)
+
+
+def test_c4_full_batch(torch_dev, ctx):
+    torch = torch_dev
+    log("c4: generating 256 images")
+    images = [bench._gen_one(k) for k in range(256)]
+    sizes = [im.size for im in images]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    flat = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    for k, im in enumerate(images):
+        flat[int(offs[k]):int(offs[k + 1])].copy_(torch.from_numpy(im.reshape(-1)))
+    views = [flat[int(offs[k]):int(offs[k + 1])].view(images[k].shape) for k in range(len(images))]
+    log(f"c4: encoding {int(offs[-1])} pixels")
+    out, offsets, n = ctx.encode_batch(views, B_MAX, B_MIN, THR)
+    torch.cuda.synchronize()
+    o = offsets.cpu().numpy()
+    assert o[0] == 0 and o[-1] == n and np.all(np.diff(o) > 0)
+    recs = fb.to_records(out[:n])
+    for k, im in enumerate(images):
+        H, W = im.shape
+        _check_structure(recs[o[k]:o[k + 1]], W, H)
+    rng = np.random.default_rng(4)
+    sample = {int(np.argmax(sizes)), int(np.argmin(sizes))} | set(rng.choice(256, 6, replace=False).tolist())
+    for k in sorted(sample):
+        log(f"c4: oracle on image {k} ({images[k].shape[1]}x{images[k].shape[0]})")
+        want = mns.encode(images[k], B_MAX, B_MIN, THR)
+        got = recs[o[k]:o[k + 1]]
+        assert got.tobytes() == np.ascontiguousarray(want).tobytes(), k
