@@ -5,6 +5,23 @@ Device buffers are torch tensors on the context's GPU (PyTorch supplies
 memory and streams); every step of the method runs in the library's HIP
 kernels.  If libfe.so is missing or cannot be loaded, every call raises:
 there is no fallback path.
+
+Typical use::
+
+    import torch
+    from paper_1501_02894_amd import binding as fb
+
+    img = torch.from_numpy(gray_uint8_array).cuda()          # H x W, sides multiples of b_max
+    with fb.Context(0) as ctx:
+        t = ctx.encode(img, 16, 4, [300, 200])                # (n, 16) uint8 transform stream
+        out = ctx.decode(t, img.shape[1], img.shape[0], 16, 12)       # 12 iterations from grey
+        big = ctx.decode_zoom(t, img.shape[1], img.shape[0], 16, 2, 12)  # twice the size
+        data, nbits = fb.fe_pack(ctx.handle, t, img.shape[1], img.shape[0], 16, 4)  # the file
+    records, info = fb.fe_unpack(data.cpu().numpy().tobytes()[: (nbits + 7) // 8], nbits)
+
+``encode_batch`` encodes a list of images in one launch, ``Plan`` records a
+batch as a HIP graph, ``Server`` serves a stream of requests, and
+``full_search=True`` / ``local_search=True`` select the search baselines.
 """
 from __future__ import annotations
 
