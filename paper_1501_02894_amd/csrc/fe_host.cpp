@@ -94,6 +94,8 @@ struct fe_plan {
   uint64_t* masks = nullptr;
   uint32_t* chunk_sum = nullptr;
   uint64_t* chunk_base = nullptr;
+  uint4* fine_list = nullptr;     // trees down to 2 x 2: the listed 4 x 4 ranges
+  uint32_t* fine_count = nullptr;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -281,36 +283,40 @@ fe_status build_table(const fe_image_desc* imgs, uint32_t n_imgs, const fe_param
   return FE_OK;
 }
 
+// Tile shape of an encode call with L fused levels.  The context's choice
+// (or the default); but a call too small to give the default shape a
+// workgroup per CU (a single 512 x 512 image, say) takes the shape with the
+// fewest tiles per workgroup, unless the caller set one.  Trees down to
+// 2 x 2 (ext) use the shapes their EXT form is built for: the default, or
+// the smallest of 16 -> 4 (4 x 2) and 8 -> 4 (4 x 4).
+fe::TileShape choose_shape(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p, int L,
+                           bool ext) {
+  const int bmax = (int)p->b_max;
+  fe::TileShape cand[16];
+  const int k = fe::encode_shapes(bmax, L, cand, 16);
+  if (k <= 0) return fe::TileShape{0, 0};
+  fe::TileShape shape = ext ? cand[0] : pick_shape(ctx, bmax, L);
+  if (!ext && ctx->shape_override[bmax][L].gx > 0) return shape;
+  uint64_t all_tiles = 0;
+  for (uint32_t i = 0; i < n_imgs; ++i) all_tiles += (uint64_t)(imgs[i].width / p->b_max) * (imgs[i].height / p->b_max);
+  if (all_tiles / (uint64_t)(cand[0].gx * cand[0].gy) >= kSmallCallGroups) return shape;
+  shape = cand[0];
+  for (int i = 1; i < k; ++i)
+    if (cand[i].gx * cand[i].gy < shape.gx * shape.gy) shape = cand[i];
+  if (ext && !((bmax == 16 && shape.gx == 4 && shape.gy == 2) || (bmax == 8 && shape.gx == 4 && shape.gy == 4)))
+    shape = cand[0];
+  return shape;
+}
+
 // Shared MNS encode of a list of images with common parameters.
 fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
                         fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
-  // b_min = 2: the fused kernel runs the tree down to 4 x 4 (its EXT form,
-  // default tile shape) and the 2 x 2 level follows in a kernel of its own
+  // b_min = 2: the fused kernel runs the tree down to 4 x 4 (its EXT form)
+  // and the 2 x 2 level follows in a kernel of its own
   const bool ext = p->b_min < 4;
   const int L = fe::levels_of(p->b_max, ext ? 4u : p->b_min);   // fused levels
   const int bmax = (int)p->b_max;
-  fe::TileShape shape = pick_shape(ctx, bmax, L);
-  if (ext) {
-    fe::TileShape first[16];
-    shape = fe::encode_shapes(bmax, L, first, 16) > 0 ? first[0] : fe::TileShape{0, 0};
-  }
-  if (ext || ctx->shape_override[bmax][L].gx <= 0) {
-    // a call too small to give the default shape a workgroup per CU (a
-    // single 512 x 512 image, say) takes the shape with the fewest tiles
-    // per workgroup: more, shorter workgroups
-    uint64_t all_tiles = 0;
-    for (uint32_t k = 0; k < n_imgs; ++k) all_tiles += (uint64_t)(imgs[k].width / p->b_max) * (imgs[k].height / p->b_max);
-    fe::TileShape cand[16];
-    const int k = fe::encode_shapes(bmax, L, cand, 16);
-    if (k > 0 && all_tiles / (uint64_t)(cand[0].gx * cand[0].gy) < kSmallCallGroups) {
-      shape = cand[0];
-      for (int i = 1; i < k; ++i)
-        if (cand[i].gx * cand[i].gy < shape.gx * shape.gy) shape = cand[i];
-      // the EXT form is built for (16, 3, 4 x 2) and (8, 2, 4 x 4) besides the defaults
-      if (ext && !((bmax == 16 && shape.gx == 4 && shape.gy == 2) || (bmax == 8 && shape.gx == 4 && shape.gy == 4)))
-        shape = cand[0];
-    }
-  }
+  const fe::TileShape shape = choose_shape(ctx, imgs, n_imgs, p, L, ext);
   if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
   const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));
   std::vector<fe::ImgDev> table;
@@ -976,19 +982,21 @@ std::vector<hipGraphNode_t> chain_of(hipGraph_t g) {
 // own[2] between encode and the first ordering kernel, own[3] after the
 // last.  Instantiates the copy.  Returns false (and leaves the plan
 // untouched) if any step fails.
-bool add_timing_nodes(fe_plan* pl) {
+bool add_timing_nodes(fe_plan* pl, size_t i_enc, size_t i_ord) {
   hipGraph_t g = nullptr;
   if (hipGraphClone(&g, pl->graph) != hipSuccess) return false;
   bool ok = false;
   do {
+    // chain positions: the encode kernels are c[i_enc] .. c[i_ord - 1], the
+    // ordering kernels c[i_ord] ..
     std::vector<hipGraphNode_t> c = chain_of(g);
-    if (c.size() < 3) break;
-    hipGraphNode_t prep = c[0], enc = c[1], ord = c[2], last = c.back();
+    if (i_enc == 0 || i_ord <= i_enc || c.size() <= i_ord) break;
+    hipGraphNode_t prep = c[i_enc - 1], enc = c[i_enc], enc_end = c[i_ord - 1], ord = c[i_ord], last = c.back();
     hipGraphNode_t n[4] = {};
     if (hipGraphAddEventRecordNode(&n[0], g, &prep, 1, pl->own[0]) != hipSuccess) break;
     if (hipGraphAddDependencies(g, &n[0], &enc, 1) != hipSuccess) break;
-    if (hipGraphAddEventRecordNode(&n[1], g, &enc, 1, pl->own[1]) != hipSuccess) break;
-    if (hipGraphAddEventRecordNode(&n[2], g, &enc, 1, pl->own[2]) != hipSuccess) break;
+    if (hipGraphAddEventRecordNode(&n[1], g, &enc_end, 1, pl->own[1]) != hipSuccess) break;
+    if (hipGraphAddEventRecordNode(&n[2], g, &enc_end, 1, pl->own[2]) != hipSuccess) break;
     if (hipGraphAddDependencies(g, &n[1], &ord, 1) != hipSuccess) break;
     if (hipGraphAddDependencies(g, &n[2], &ord, 1) != hipSuccess) break;
     if (hipGraphAddEventRecordNode(&n[3], g, &last, 1, pl->own[3]) != hipSuccess) break;
@@ -1016,17 +1024,18 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   *out = nullptr;
   fe_status st = check_batch(h_imgs, n_imgs, p, d_out, d_offsets);
   if (st != FE_OK) return st;
-  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "a plan records trees that stop at 4 x 4 (b_min >= 4)");
   DeviceGuard g(ctx->device);
-  const int L = fe::levels_of(p->b_max, p->b_min);
+  const bool ext = p->b_min < 4;   // down to 2 x 2: EXT form, then the 2 x 2 level
+  const int L = fe::levels_of(p->b_max, ext ? 4u : p->b_min);
   const int bmax = (int)p->b_max;
-  const fe::TileShape shape = pick_shape(ctx, bmax, L);
+  const fe::TileShape shape = choose_shape(ctx, h_imgs, n_imgs, p, L, ext);
   if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
   std::vector<fe::ImgDev> table;
   uint64_t tiles = 0;
   uint32_t wgs = 0;
   if ((st = build_table(h_imgs, n_imgs, p, shape, table, tiles, wgs)) != FE_OK) return st;
-  const int cells = 1 << (2 * (L - 1));
+  const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));
+  const uint64_t fine_max = ext ? tiles * (uint64_t)(bmax / 4) * (uint64_t)(bmax / 4) : 0;
   const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
   fe_plan* pl = new fe_plan();
   pl->device = ctx->device;
@@ -1042,6 +1051,8 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->masks), std::max<size_t>(tiles, 1) * 8);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_sum), std::max<size_t>(chunks, 1) * 4);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_base), (chunks + 1) * 8);
+  if (e == hipSuccess && ext) e = hipMalloc(reinterpret_cast<void**>(&pl->fine_list), std::max<uint64_t>(fine_max, 1) * 16);
+  if (e == hipSuccess && ext) e = hipMalloc(reinterpret_cast<void**>(&pl->fine_count), 4);
   if (e == hipSuccess) e = hipMemcpy(pl->d_table, host.data(), slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
   for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreate(&pl->own[k]);
@@ -1062,10 +1073,31 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
   a.staging = pl->staging;
   a.masks = pl->masks;
+  a.fine_list = pl->fine_list;
+  a.fine_count = pl->fine_count;
   e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    // chain: prep, [zero count], encode, [2 x 2 level], ordering; the count
+    // is cleared by a kernel, not a memset node
     hipError_t le = fe::launch_block_prep(pl->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, pl->blocks, pl->capture);
-    if (le == hipSuccess) le = fe::launch_mns_tiles(bmax, L, shape, a, pl->capture);
+    if (le == hipSuccess && ext) le = fe::launch_zero_u32(pl->fine_count, 1, pl->capture);
+    if (le == hipSuccess)
+      le = ext ? fe::launch_mns_tiles_ext(bmax, L, shape, a, pl->capture) : fe::launch_mns_tiles(bmax, L, shape, a, pl->capture);
+    if (le == hipSuccess && ext) {
+      fe::FinishArgs f{};
+      f.imgs = pl->d_table;
+      f.n_imgs = n_imgs;
+      f.list = pl->fine_list;
+      f.count = pl->fine_count;
+      f.gx = (uint32_t)shape.gx;
+      f.level = (uint32_t)L;
+      f.thr = p->mse_thr[L - 1];
+      f.phase2 = a.phase2;
+      f.identity_only = a.identity_only;
+      f.staging = pl->staging;
+      f.masks = pl->masks;
+      le = fe::launch_fine_finish(f, fine_max, pl->capture);
+    }
     if (le == hipSuccess)
       le = fe::launch_scatter(pl->d_table, n_imgs, table_chunk_img(pl->d_table, n_imgs), tiles, cells, shape,
                               pl->masks, pl->chunk_sum, pl->chunk_base,
@@ -1077,11 +1109,12 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     fe_plan_destroy(pl);
     return hip_fail(e, "plan capture");
   }
-  // The capture is a chain: prep, encode, then the ordering kernels.  If
-  // timing is on, a copy of it gets event-record nodes before and after the
-  // encode kernel and after the last ordering kernel; if that fails, or
-  // timing is off, the plain chain is used and launches are not timed.
-  pl->timed = ctx->timing && add_timing_nodes(pl);
+  // The capture is a chain: prep, [zero count], encode, [2 x 2 level], then
+  // the ordering kernels.  If timing is on, a copy of it gets event-record
+  // nodes before and after the encode kernels and after the last ordering
+  // kernel; if that fails, or timing is off, the plain chain is used and
+  // launches are not timed.
+  pl->timed = ctx->timing && (ext ? add_timing_nodes(pl, 2, 4) : add_timing_nodes(pl, 1, 2));
   if (!pl->timed) {
     e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1130,7 +1163,7 @@ void fe_plan_destroy(fe_plan* pl) {
   for (hipEvent_t ev : pl->own)
     if (ev) (void)hipEventDestroy(ev);
   for (void* q : {(void*)pl->d_table, (void*)pl->blocks, (void*)pl->staging, (void*)pl->masks,
-                  (void*)pl->chunk_sum, (void*)pl->chunk_base})
+                  (void*)pl->chunk_sum, (void*)pl->chunk_base, (void*)pl->fine_list, (void*)pl->fine_count})
     if (q) (void)hipFree(q);
   delete pl;
 }

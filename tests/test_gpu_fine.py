@@ -3,7 +3,7 @@ four levels, 16 x 16 to 2 x 2), through the C ABI.
 
 The encoder for b_min = 2 (the fused kernel down to 4 x 4, then the 2 x 2
 level with domain means formed from pixels at either phase) must give the
-oracle's stream byte for byte, alone and in a batch; both
+oracle's stream byte for byte, alone, in a batch and replayed as a plan; both
 decoders, zoom decoding and the compressed file must take such streams (the
 tile decoder steps aside for blocks under 4 x 4, and takes them again once a
 zoom has made them 4 x 4 or larger)."""
@@ -171,6 +171,40 @@ def test_batch(torch_dev, ctx, b_max, thr):
         assert_same_stream(got[offs[k]:offs[k + 1]], mns.encode(im, b_max, 2, thr))
 
 
+@pytest.mark.parametrize("timing", [False, True])
+def test_plan_replays(torch_dev, ctx, timing):
+    # the batch recorded as a HIP graph (zeroing kernel, EXT encode, 2 x 2
+    # level, ordering): every replay equals the eager batch and the oracle,
+    # with other work and synchronisations between replays
+    torch = torch_dev
+    log(f"fine plan timing={timing}")
+    imgs = [synth.workload("c1"), synth.noise_1f(48, 80, 71), synth.workload("c2")]
+    views = [dev(torch, im) for im in imgs]
+    thr = [300, 200, 100]
+    out, offs, n = ctx.encode_batch(views, 16, 2, thr)
+    eager = out[:n].cpu().numpy().tobytes()
+    eager_offs = offs.cpu().numpy()
+    got = fb.to_records(out[:n])
+    for k, im in enumerate(imgs):
+        assert_same_stream(got[eager_offs[k]:eager_offs[k + 1]], mns.encode(im, 16, 2, thr))
+    out2 = torch.empty_like(out)
+    offs2 = torch.zeros_like(offs)
+    fb.fe_timing_enable(ctx.handle, timing)
+    try:
+        with fb.Plan(ctx, views, 16, 2, thr, out2, offs2) as plan:
+            for _ in range(3):
+                out2.zero_()
+                plan.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(offs2.cpu().numpy(), eager_offs)
+                assert out2[:n].cpu().numpy().tobytes() == eager
+                ctx.encode_batch(views[:1], 8, 2, [300, 150])   # other work in between
+                torch.cuda.synchronize()
+    finally:
+        fb.fe_timing_enable(ctx.handle, False)
+        fb.fe_timing_read(ctx.handle)
+
+
 def test_paths_that_do_not_take_2x2(torch_dev, ctx):
     log("fine rejections")
     img = dev(torch_dev, synth.workload("c1"))
@@ -178,9 +212,5 @@ def test_paths_that_do_not_take_2x2(torch_dev, ctx):
         ctx.encode(img, 8, 2, [300, 150], full_search=True)
     with pytest.raises(fb.FeError):
         ctx.encode(img, 8, 2, [300, 150], local_search=True)
-    out = torch_dev.empty((fb.fe_max_transforms(64, 64, 2), 16), dtype=torch_dev.uint8, device="cuda")
-    offs = torch_dev.zeros(2, dtype=torch_dev.int64, device="cuda")
-    with pytest.raises(fb.FeError):
-        fb.Plan(ctx, [img], 8, 2, [300, 150], out, offs)
     with pytest.raises(fb.FeError):
         ctx.encode(img, 32, 2, [1, 1, 1, 1])        # five levels
