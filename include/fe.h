@@ -128,8 +128,8 @@ typedef struct fe_transform {
  *                 2 <= b_min <= b_max, 4 <= b_max <= 32 and at most four
  *                 levels (two level bits, Sec. 3.3; the paper's tree is
  *                 16 -> 2).  b_min = 2 is taken by fe_encode,
- *                 fe_encode_batch and plans (MNS or no-search, b_max 4, 8 or
- *                 16), not by the server or the exhaustive and local
+ *                 fe_encode_batch, plans and the server (MNS or no-search,
+ *                 b_max 4, 8 or 16), not by the exhaustive and local
  *                 searches.
  *   n_thr         number of thresholds = L - 1, L = log2(b_max/b_min) + 1.
  *   flags         FE_PHASE2, FE_FULL_SEARCH, FE_IDENTITY_ONLY (MNS only),

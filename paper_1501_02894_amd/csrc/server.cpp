@@ -119,7 +119,11 @@ struct Request {
 struct fe_server {
   int device = 0;
   fe_params params{};
-  int L = 0, cells = 0;
+  int L = 0, cells = 0;                  // fused levels; record cells per tile
+  bool ext = false;                      // trees down to 2 x 2 (b_min = 2)
+  uint4* fine_list = nullptr;            // ext: the step's 4 x 4 ranges that go on to 2 x 2
+  uint32_t* fine_count = nullptr;
+  uint64_t fine_cap = 0;
   fe::TileShape shape{};
   hipStream_t compute = nullptr, copy = nullptr;
   uint8_t* dev_base = nullptr;           // byte arena memory
@@ -268,13 +272,14 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   lk.lock();
   fe::BlockDesc* hd = s->h_desc[slot];
   uint32_t n = 0;
-  std::vector<Request*> finishing, first_time;
+  std::vector<Request*> finishing, first_time, in_step;
   for (Request* r : ready) {
     if (n >= s->step_blocks) break;
     if (!r->waited) {
       first_time.push_back(r);
       r->waited = true;
     }
+    in_step.push_back(r);
     while (r->next_block < r->blocks && n < s->step_blocks) {
       const uint64_t b = r->next_block++;
       const uint32_t gyi = (uint32_t)(b / r->groups_x), gxi = (uint32_t)(b - (uint64_t)gyi * r->groups_x);
@@ -306,8 +311,26 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     im.groups_x = r->groups_x;
     im.groups_y = (uint32_t)(r->blocks / r->groups_x);
   }
-  const size_t upload = (size_t)n * sizeof(fe::BlockDesc) + finishing.size() * sizeof(fe::ImgDev);
+  // ext: the step's requests by tile-arena base, for the 2 x 2 level to
+  // find each listed range's image
+  fe::ImgDev* hx = him + finishing.size();
+  if (s->ext) {
+    std::sort(in_step.begin(), in_step.end(), [](const Request* x, const Request* y) { return x->tile_base < y->tile_base; });
+    for (size_t j = 0; j < in_step.size(); ++j) {
+      const Request* r = in_step[j];
+      fe::ImgDev& im = hx[j];
+      im = fe::ImgDev{};
+      im.data = s->dev_base + r->img_off;
+      im.width = r->w;
+      im.height = r->h;
+      im.stride = r->pitch;
+      im.tile_first = r->tile_base;
+    }
+  }
+  const size_t n_x = s->ext ? in_step.size() : 0;
+  const size_t upload = (size_t)n * sizeof(fe::BlockDesc) + (finishing.size() + n_x) * sizeof(fe::ImgDev);
   const fe::ImgDev* dim = reinterpret_cast<const fe::ImgDev*>(s->d_desc[slot] + n);
+  const fe::ImgDev* dx_tab = dim + finishing.size();
   lk.unlock();
   hipError_t e = hipSuccess;
   for (Request* r : first_time)
@@ -323,7 +346,30 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)s->params.n_thr ? s->params.mse_thr[l] : 0u;
     a.staging = s->staging;
     a.masks = s->masks;
-    e = fe::launch_mns_tiles((int)s->params.b_max, s->L, s->shape, a, s->compute);
+    if (!s->ext) {
+      e = fe::launch_mns_tiles((int)s->params.b_max, s->L, s->shape, a, s->compute);
+    } else {
+      a.fine_list = s->fine_list;
+      a.fine_count = s->fine_count;
+      e = fe::launch_zero_u32(s->fine_count, 1, s->compute);
+      if (e == hipSuccess) e = fe::launch_mns_tiles_ext((int)s->params.b_max, s->L, s->shape, a, s->compute);
+      if (e == hipSuccess) {
+        fe::FinishArgs f{};
+        f.imgs = dx_tab;
+        f.n_imgs = (uint32_t)n_x;
+        f.list = s->fine_list;
+        f.count = s->fine_count;
+        f.gx = (uint32_t)s->shape.gx;
+        f.level = (uint32_t)s->L;
+        f.thr = s->params.mse_thr[s->L - 1];
+        f.phase2 = a.phase2;
+        f.identity_only = a.identity_only;
+        f.staging = s->staging;
+        f.masks = s->masks;
+        const uint64_t bm4 = s->params.b_max / 4;
+        e = fe::launch_fine_finish(f, (uint64_t)n * (uint64_t)(s->shape.gx * s->shape.gy) * bm4 * bm4, s->compute);
+      }
+    }
   }
   for (size_t j = 0; j < finishing.size(); ++j) {
     Request* r = finishing[j];
@@ -418,21 +464,23 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   fe_status st = fe::check_params(p);
   if (st != FE_OK) return st;
   if (p->flags & (FE_FULL_SEARCH | FE_LOCAL_SEARCH)) return fe::fail(FE_ERR_INVALID, "the server runs MNS only");
-  if (p->b_min < 4) return fe::fail(FE_ERR_INVALID, "the server serves trees that stop at 4 x 4 (b_min >= 4)");
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
     return fe::fail(FE_ERR_DEVICE, "no HIP device %d", device);
   fe_server* s = new fe_server();
   s->device = device;
   s->params = *p;
-  s->L = fe::levels_of(p->b_max, p->b_min);
-  s->cells = 1 << (2 * (s->L - 1));
-  uint32_t gx[16], gy[16];
-  if (fe_tile_shapes(p->b_max, p->b_min, gx, gy, 16) == 0) {
+  // b_min = 2: the fused kernel's EXT form down to 4 x 4 (default shape),
+  // then the 2 x 2 level; record cells are 2 x 2 units
+  s->ext = p->b_min < 4;
+  s->L = fe::levels_of(p->b_max, s->ext ? 4u : p->b_min);
+  s->cells = 1 << (2 * (s->L - 1 + (s->ext ? 1 : 0)));
+  fe::TileShape shapes[16];
+  if (fe::encode_shapes((int)p->b_max, s->L, shapes, 16) == 0) {
     delete s;
     return fe::fail(FE_ERR_INVALID, "no kernel for these block sizes");
   }
-  s->shape = fe::TileShape{(int)gx[0], (int)gy[0]};
+  s->shape = shapes[0];
   s->max_slots = max_slots;
   s->step_blocks = step_blocks;
   // a quarter of the budget holds tile slots (records + masks), the rest
@@ -448,14 +496,21 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
-    // per step: the block descriptors, then one image entry per finishing request
+    // per step: the block descriptors, then one image entry per finishing
+    // request and (ext) one per request of the step
     ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]),
-                       (size_t)step_blocks * (sizeof(fe::BlockDesc) + sizeof(fe::ImgDev)),
+                       (size_t)step_blocks * (sizeof(fe::BlockDesc) + 2 * sizeof(fe::ImgDev)),
                        hipHostMallocDefault) == hipSuccess &&
          hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]),
-                   (size_t)step_blocks * (sizeof(fe::BlockDesc) + sizeof(fe::ImgDev))) ==
+                   (size_t)step_blocks * (sizeof(fe::BlockDesc) + 2 * sizeof(fe::ImgDev))) ==
              hipSuccess &&
          hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
+  if (ok && s->ext) {
+    const uint64_t bm4 = p->b_max / 4;
+    s->fine_cap = (uint64_t)step_blocks * (uint64_t)(s->shape.gx * s->shape.gy) * bm4 * bm4;
+    ok = hipMalloc(reinterpret_cast<void**>(&s->fine_list), std::max<uint64_t>(s->fine_cap, 1) * 16) == hipSuccess &&
+         hipMalloc(reinterpret_cast<void**>(&s->fine_count), 4) == hipSuccess;
+  }
   s->ev_copied.assign(max_slots, nullptr);
   s->ev_done.assign(max_slots, nullptr);
   for (uint32_t k = 0; ok && k < max_slots; ++k)
@@ -501,6 +556,8 @@ void fe_server_destroy(fe_server* s) {
     if (ev) (void)hipEventDestroy(ev);
   if (s->dev_base) (void)hipFree(s->dev_base);
   if (s->staging) (void)hipFree(s->staging);
+  if (s->fine_list) (void)hipFree(s->fine_list);
+  if (s->fine_count) (void)hipFree(s->fine_count);
   if (s->masks) (void)hipFree(s->masks);
   if (s->host_base) (void)hipHostFree(s->host_base);
   if (s->compute) (void)hipStreamDestroy(s->compute);

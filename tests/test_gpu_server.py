@@ -167,3 +167,18 @@ def test_server_pinned_submit(torch_dev, ctx):
         assert ei.value.status == fb.FE_ERR_INVALID
     for k, im in enumerate(imgs):
         assert res[k][0].tobytes() == alone(torch_dev, ctx, im).tobytes()
+
+
+@pytest.mark.parametrize("budget,step_blocks", [(8 << 30, 256), (48 << 20, 8)])
+def test_server_2x2_tree(torch_dev, ctx, budget, step_blocks):
+    # the paper's 16 -> 2 tree served: each result equals the oracle, in a
+    # mix, with small steps that spread an image over several of them
+    thr = [300, 200, 100]
+    imgs = mixed_images(10, 7, 64, 512)
+    log(f"server 16 -> 2, budget {budget >> 20} MiB, {step_blocks}-block steps")
+    with fb.Server(16, 2, thr, hbm_budget=budget, host_budget=64 << 20, max_slots=8,
+                   step_blocks=step_blocks) as srv:
+        reqs = [srv.submit(im) for im in imgs]
+        res = drain(srv, reqs)
+    for k, im in enumerate(imgs):
+        assert res[k][0].tobytes() == np.ascontiguousarray(mns.encode(im, 16, 2, thr)).tobytes(), k
