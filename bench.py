@@ -336,32 +336,38 @@ def bench_paper_tree(fb, ctx, img, thr4, thr2, reps=5):
     return res
 
 
-def bench_tradeoff(fb, ctx, images, b_max=16, b_min=4, reps=5):
+def bench_tradeoff(fb, ctx, images, b_max=16, reps=5):
     """No-search (phase 1 only) against MNS (Technique 1 on) over a sweep of
-    thresholds, with the paper's codes (identity only, 14-bit phase 1): per
-    point the file size (bpp), the PSNR after 12 decoder iterations from
-    grey, and the encode time (fused kernel, HIP events; call wall time)."""
+    thresholds, with the paper's codes (identity only, 14-bit phase 1), for
+    the 16 -> 4 tree and the paper's 16 -> 2 tree: per point the file size
+    (bpp), the PSNR after 12 decoder iterations from grey, and the encode
+    time (encode kernels, HIP events; call wall time)."""
     import torch
     pts = []
     # t2 from 100 to about 900 in steps of 1.15, t1 = 1.5 t2 (the transition
-    # from 4 x 4 blocks to whole tiles lies in this range on these images)
-    sweep = [(int(round(1.5 * 100 * 1.15 ** k)), int(round(100 * 1.15 ** k))) for k in range(16)]
+    # from 4 x 4 blocks to whole tiles lies in this range on these images);
+    # the 2 x 2 level's threshold t3 = t2 / 1.5
+    base = [100 * 1.15 ** k for k in range(16)]
+    sweeps = {4: [(int(round(1.5 * v)), int(round(v))) for v in base],
+              2: [(int(round(1.5 * v)), int(round(v)), int(round(v / 1.5))) for v in base]}
     for name, img in images.items():
         H, W = img.shape
         t = torch.from_numpy(img).cuda()
-        for phase2 in (False, True):
-            for thr in sweep:
-                p = fb.make_params(b_max, b_min, thr, phase2=phase2, identity_only=True)
-                recs = fb.fe_encode(ctx.handle, t, p)
-                kms, _, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE, lambda: fb.fe_encode(ctx.handle, t, p), reps)
-                _, nbits = fb.fe_pack(ctx.handle, recs, W, H, b_max, b_min, isometry=False)
-                dec = fb.fe_decode(ctx.handle, recs, W, H, b_max, 12).cpu().numpy().astype(np.float64)
-                mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
-                pts.append({"image": name, "method": "mns" if phase2 else "no-search", "thresholds": list(thr),
-                            "transforms": int(recs.shape[0]),
-                            "phase2_transforms": int((recs[:, 9] != 0).sum().item()), "bits": nbits,
-                            "bpp": nbits / (W * H), "psnr_db": 10.0 * np.log10(255.0 ** 2 / mse),
-                            "kernel_ms": kms, "call_ms": wall})
+        for b_min in (4, 2):
+            for phase2 in (False, True):
+                for thr in sweeps[b_min]:
+                    p = fb.make_params(b_max, b_min, thr, phase2=phase2, identity_only=True)
+                    recs = fb.fe_encode(ctx.handle, t, p)
+                    kms, _, wall = timed_kernel(fb, ctx, fb.FE_TIMING_ENCODE, lambda: fb.fe_encode(ctx.handle, t, p), reps)
+                    _, nbits = fb.fe_pack(ctx.handle, recs, W, H, b_max, b_min, isometry=False)
+                    dec = fb.fe_decode(ctx.handle, recs, W, H, b_max, 12).cpu().numpy().astype(np.float64)
+                    mse = float(np.mean((dec - img.astype(np.float64)) ** 2))
+                    pts.append({"image": name, "tree": f"{b_max}->{b_min}", "method": "mns" if phase2 else "no-search",
+                                "thresholds": list(thr),
+                                "transforms": int(recs.shape[0]),
+                                "phase2_transforms": int((recs[:, 9] != 0).sum().item()), "bits": nbits,
+                                "bpp": nbits / (W * H), "psnr_db": 10.0 * np.log10(255.0 ** 2 / mse),
+                                "kernel_ms": kms, "call_ms": wall})
     return pts
 
 
@@ -514,7 +520,8 @@ def main():
                 "rough 1/f noise (beta 1.5)": synth.noise_1f(512, 512, 22, beta=1.5)}
         pts = bench_tradeoff(fb, ctx, imgs)
         ctx.close()
-        print(json.dumps({"workload": "no-search vs MNS, 512^2, 16 -> 4, identity-only codes", "points": pts}),
+        print(json.dumps({"workload": "no-search vs MNS, 512^2, 16 -> 4 and 16 -> 2, identity-only codes",
+                          "points": pts}),
               flush=True)
         return
     if args.paper_tree:
