@@ -502,7 +502,7 @@ def main():
                     help="only the exhaustive-search encode of C2 (512^2, 16 -> 4) (a profiling workload)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -20,7 +20,7 @@ Readings (the paper gives the fields and their widths, not a file layout):
 * a 64-bit header comes first: W - 1 (16 bits), H - 1 (16), log2 B_max (3),
   log2 B_min (3), the isometry flag (1), 25 zero bits;
 * the phase bit is 1 for phase 2; the level number is the 0-based level;
-* this build's phase 1 also fits the 8 isometries: with the isometry flag
+* the encoder's phase 1 also fits the 8 isometries: with the isometry flag
   set each phase-1 block stores e in 3 more bits (17 bits); without it the
   stream must hold the identity only (encode with isometries off) and the
   phase-1 code is the paper's 14 bits;

@@ -1,4 +1,4 @@
-// Host driver of the C ABI: contexts, scratch management and the launch
+// Host side of the C ABI: contexts, scratch management and the launch
 // sequences of encode / batch encode / decode / the stand-alone steps.
 #include <hip/hip_runtime.h>
 #include <string.h>
