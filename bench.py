@@ -325,6 +325,12 @@ def bench_paper_tree(fb, ctx, img, thr4, thr2, reps=5):
                      "bpp": nbits / (W * H), "psnr_db_12_iters": 10.0 * np.log10(255.0 ** 2 / mse),
                      "decoder": "tiles" if ctx.decode_last() == fb.FE_DECODE_TILES else "records",
                      "pixels_per_s": W * H / (kms / 1e3)}
+        # decode iteration time with either decoder
+        for mode, key in ((fb.FE_DECODE_AUTO, "decode_iter_ms"), (fb.FE_DECODE_RECORDS, "decode_iter_ms_records")):
+            fb.fe_decode_set_mode(ctx.handle, mode)
+            dms, _, _ = timed_kernel(fb, ctx, fb.FE_TIMING_DECODE, lambda: fb.fe_decode(ctx.handle, recs, W, H, 16, 12), 3)
+            res[name][key] = dms
+        fb.fe_decode_set_mode(ctx.handle, fb.FE_DECODE_AUTO)
         if b_min == 4:
             zoom = {}
             for z in (1, 2):

@@ -297,9 +297,10 @@ fe_status fe_decode(fe_ctx* ctx, const fe_transform* d_t, size_t n, uint32_t wid
  * of b_max (each at least 2 b_max), d_out is 4-byte aligned, and the stream
  * lists the tiles in raster order with each tile's transforms partitioning
  * it in Morton order (the order fe_encode writes) with co-centred domains
- * (Sec. 3.1) and maps no block under 4 x 4 pixels (no 2 x 2 range, no
- * phase-2 transform of side 4), and its plan (2.3 KB per 64 x 64-pixel block, kept in the
- * context) can be allocated.  The record decoder (one wave per transform)
+ * (Sec. 3.1), and its plan (2.3 KB per 64 x 64-pixel block, kept in the
+ * context) can be allocated; the 2 x 2 pieces of such a stream (2 x 2
+ * ranges, phase-2 transforms of side 4) are decoded beside it by a kernel
+ * of their own each iteration.  The record decoder (one wave per transform)
  * runs any valid stream.  fe_decode_set_mode selects FE_DECODE_AUTO (the default: tiles
  * when allowed) or FE_DECODE_RECORDS for a context; fe_decode_last returns
  * FE_DECODE_TILES or FE_DECODE_RECORDS for the last fe_decode on ctx.

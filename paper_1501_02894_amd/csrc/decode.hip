@@ -273,6 +273,8 @@ __global__ __launch_bounds__(256) void tile_setup_kernel(DecodeArgs a, uint32_t*
 // the plan is fixed by the stream; only Sum d changes between iterations.
 constexpr int kDecTile = 64;                 // block side (pixels)
 constexpr int kDecCells = (kDecTile / 4) * (kDecTile / 4);
+constexpr int kDecSpare = kDecCells - 1;        // plan slot of the cells of 2 x 2 blocks
+constexpr uint32_t kDecSkip = 1u << 23;         // piece word-0 flag: cell left to the small-piece kernel
 
 struct DecRegion {
   int X0, Y0, bw, bh;   // block origin and size (pixels)
@@ -304,8 +306,10 @@ __device__ __forceinline__ DecRegion dec_region(int blk, int W, int H, int bm) {
 // consecutive records per tile row), expand them into pieces and the cell
 // map.  Runs once per decode call.
 __global__ __launch_bounds__(256) void dec_plan_kernel(DecodeArgs a, const uint32_t* __restrict__ tile_start,
-                                                       uint8_t* __restrict__ cells, uint2* __restrict__ pieces) {
-  __shared__ uint32_t s_run0[kDecTile / 4], s_runs[kDecTile / 4 + 1], s_count;
+                                                       uint8_t* __restrict__ cells, uint2* __restrict__ pieces,
+                                                       uint32_t* __restrict__ small_list,
+                                                       uint32_t* __restrict__ small_count) {
+  __shared__ uint32_t s_run0[kDecTile / 4], s_runs[kDecTile / 4 + 1], s_count, s_small;
   __shared__ uint8_t s_cell[kDecCells];
   const int tid = threadIdx.x, blk = blockIdx.x;
   const int W = (int)a.width, H = (int)a.height, bm = (int)a.b_max;
@@ -317,7 +321,10 @@ __global__ __launch_bounds__(256) void dec_plan_kernel(DecodeArgs a, const uint3
     s_run0[tid] = tile_start[t0];
     s_runs[tid + 1] = tile_start[t0 + gxn] - tile_start[t0];
   }
-  if (tid == 0) s_count = 0;
+  if (tid == 0) {
+    s_count = 0;
+    s_small = 0;
+  }
   __syncthreads();
   if (tid == 0) {
     s_runs[0] = 0;
@@ -329,8 +336,18 @@ __global__ __launch_bounds__(256) void dec_plan_kernel(DecodeArgs a, const uint3
   for (int j = tid; j < nrec; j += 256) {
     int row = 0;
     while (row + 1 < gyn && (int)s_runs[row + 1] <= j) ++row;
-    const Fields f = unpack(a.recs[s_run0[row] + (uint32_t)(j - (int)s_runs[row])]);
+    const uint32_t ri = s_run0[row] + (uint32_t)(j - (int)s_runs[row]);
+    const Fields f = unpack(a.recs[ri]);
     const int B = bm >> f.level;
+    if (B < 4 || (f.flags != 0 && B < 8)) {
+      // a block of 2 x 2 pieces: listed for the small-piece kernel; its
+      // cell points at the block's spare slot, which tells the tile kernel
+      // to leave the cell alone
+      small_list[atomicAdd(small_count, 1u)] = ri;
+      s_small = 1;
+      s_cell[((f.y - g.Y0) >> 2) * (kDecTile / 4) + ((f.x - g.X0) >> 2)] = (uint8_t)kDecSpare;
+      continue;
+    }
     const int np = f.flags ? 4 : 1, b = f.flags ? B / 2 : B;
     const uint32_t p0 = atomicAdd(&s_count, (uint32_t)np);
     int c1 = 0, c2 = 0, delta = 0;
@@ -359,6 +376,9 @@ __global__ __launch_bounds__(256) void dec_plan_kernel(DecodeArgs a, const uint3
   }
   __syncthreads();
   cells[(size_t)blk * kDecCells + tid] = s_cell[tid];
+  // with a 2 x 2 block in it, the block has at most 255 pieces, so the
+  // spare slot is free: a piece that only marks its cells
+  if (tid == 0 && s_small) out[kDecSpare] = make_uint2(kDecSkip, 0u);
 }
 
 template <int BMAX>
@@ -451,7 +471,7 @@ __global__ __launch_bounds__(256) void dec_iter_kernel(DecodeArgs a, uint32_t n_
     atomicAdd(&s_sd[p], acc);
   }
   __syncthreads();
-  if (!live) return;
+  if (!live || (pc.x & kDecSkip)) return;
   // ---- output: clamp((c (n d - Sum d) + L) >> shift) per pixel, divided by
   // 20 for a phase-2 piece
   const int shift = ph2 ? 2 * lb : 3 + 2 * lb;
@@ -493,6 +513,64 @@ __global__ __launch_bounds__(256) void dec_iter_kernel(DecodeArgs a, uint32_t n_
   }
 }
 
+// The 2 x 2 pieces of a tile-decoded stream, one iteration: four lanes per
+// listed transform, one per 2 x 2 piece (a phase-2 range of side 4 has four
+// sub-blocks; a phase-1 2 x 2 range is one piece, taken by the first lane).
+// A 2 x 2 piece's domain lies at an odd origin (x - 1), so its means are
+// formed from the iterate's pixels; the arithmetic is the per-record
+// decoder's.
+constexpr unsigned kSmallGroups = 2048;
+
+__global__ __launch_bounds__(256) void small_iter_kernel(DecodeArgs a, const uint32_t* __restrict__ list,
+                                                         const uint32_t* __restrict__ count,
+                                                         const uint8_t* __restrict__ cur, uint8_t* __restrict__ nxt) {
+  const int W = (int)a.width, H = (int)a.height;
+  const uint64_t nl = 4ull * *count;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < nl; i += (uint64_t)gridDim.x * 256u) {
+    const Fields f = unpack(a.recs[list[i >> 2]]);
+    const int c = (int)(i & 3u);
+    if (!f.flags && c != 0) continue;
+    int c1 = 0, c2 = 0, delta = 0;
+    if (f.flags) phase2_consts(f.level + 1, c1, c2, delta);
+    {
+      const int px = f.x + (f.flags ? 2 * (c & 1) : 0), py = f.y + (f.flags ? 2 * (c >> 1) : 0);
+      const int ox = f.flags ? cocentred(px, 2, W) : f.dx, oy = f.flags ? cocentred(py, 2, H) : f.dy;
+      int d[2][2], sum = 0;
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+          d[i2][j2] = mean4(cur, W, ox + 2 * j2, oy + 2 * i2);
+          sum += d[i2][j2];
+        }
+      int O = f.lum, k = f.s_idx;
+      if (f.flags) {
+        const int O0 = f.lum + f.d0, O1 = f.lum + f.d1, O2 = f.lum + f.d2;
+        O = c == 0 ? O0 : (c == 1 ? O1 : (c == 2 ? O2 : 4 * f.lum - O0 - O1 - O2));
+        k = ((f.s_idx >> c) & 1) ? c2 : c1;
+      }
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+          int si = i2, sj = j2;
+          if (!f.flags) iso_src(f.iso, i2, j2, 2, si, sj);
+          // selects, not an indexed load: the four means stay in registers
+          const int dv = si ? (sj ? d[1][1] : d[1][0]) : (sj ? d[0][1] : d[0][0]);
+          int v;
+          if (!f.flags) {
+            const int num = k * (4 * dv - sum) + 32 * f.lum + 16;
+            v = num < 0 ? 0 : min(num >> 5, 255);
+          } else {
+            const int num = k * (4 * dv - sum) + 80 * O + 40;
+            v = num < 0 ? 0 : min((num >> 2) / 20, 255);
+          }
+          nxt[(size_t)(py + i2) * W + px + j2] = (uint8_t)v;
+        }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_decode_check(const DecodeArgs& a, uint32_t* bad, hipStream_t s) {
@@ -525,9 +603,19 @@ size_t decode_plan_blocks(uint32_t w, uint32_t h) {
 }
 
 hipError_t launch_decode_plan(const DecodeArgs& a, const uint32_t* tile_start, uint8_t* cells, uint2* pieces,
-                              hipStream_t s) {
+                              uint32_t* small_list, uint32_t* small_count, hipStream_t s) {
   const unsigned grid = (unsigned)decode_plan_blocks(a.width, a.height);
-  hipLaunchKernelGGL(dec_plan_kernel, dim3(grid), dim3(256), 0, s, a, tile_start, cells, pieces);
+  hipLaunchKernelGGL(dec_plan_kernel, dim3(grid), dim3(256), 0, s, a, tile_start, cells, pieces, small_list,
+                     small_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_small(const DecodeArgs& a, const uint32_t* small_list, const uint32_t* small_count,
+                               const uint8_t* cur, uint8_t* nxt, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const uint64_t want = (4 * a.n + 255) / 256;
+  const unsigned grid = (unsigned)(want < kSmallGroups ? want : kSmallGroups);
+  hipLaunchKernelGGL(small_iter_kernel, dim3(grid), dim3(256), 0, s, a, small_list, small_count, cur, nxt);
   return hipGetLastError();
 }
 

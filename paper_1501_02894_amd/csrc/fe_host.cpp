@@ -68,6 +68,8 @@ struct fe_ctx {
   size_t pack_chunk_n = 0;
   uint4* zoom_recs = nullptr;         // zoom decoding: the scaled transforms
   size_t zoom_recs_n = 0;
+  uint32_t* dec_small = nullptr;      // decoder: transforms of 2 x 2 pieces, then their count
+  size_t dec_small_n = 0;
   uint4* fine_list = nullptr;         // b_min = 2: the 4 x 4 ranges that go on to 2 x 2
   size_t fine_list_n = 0;
   uint32_t* fine_count = nullptr;
@@ -581,6 +583,7 @@ void fe_destroy(fe_ctx* c) {
   (void)hipFree(c->pack_chunk);
   (void)hipFree(c->zoom_recs);
   (void)hipFree(c->fine_list);
+  (void)hipFree(c->dec_small);
   (void)hipFree(c->fine_count);
   if (c->ev) {
     for (int i = 0; i < 2 * fe_ctx::kTimingCap; ++i)
@@ -663,6 +666,7 @@ fe_status decode_body(fe_ctx* ctx, const fe::DecodeArgs& a, uint32_t iters, cons
     fe_status st = ensure(ctx->dec_tiles, ctx->dec_tiles_n, ntiles + 1, "tile starts");
     if (st == FE_OK) st = ensure(ctx->dec_cells, ctx->dec_cells_n, nblk * 256, "decode plan cells");
     if (st == FE_OK) st = ensure(ctx->dec_pieces, ctx->dec_pieces_n, nblk * 256, "decode plan pieces");
+    if (st == FE_OK) st = ensure(ctx->dec_small, ctx->dec_small_n, (size_t)n + 1, "decode 2 x 2 list");
     if (st != FE_OK) {
       // no room for the plan: the per-record decoder needs none
       (void)hipGetLastError();
@@ -678,7 +682,9 @@ fe_status decode_body(fe_ctx* ctx, const fe::DecodeArgs& a, uint32_t iters, cons
   FE_HIP(hipStreamSynchronize(s), "transform check");
   const uint32_t bad = (uint32_t)(ctx->h_scalars[0] & 0xffffffffu);
   if (bad) return fe::fail(FE_ERR_INVALID, "%u transforms are out of range for a %ux%u image", bad, w, h);
-  const bool tiled = tiled_shape && (uint32_t)(ctx->h_scalars[0] >> 32) == 0u;
+  const uint32_t tflags = (uint32_t)(ctx->h_scalars[0] >> 32);
+  const bool tiled = tiled_shape && (tflags & 1u) == 0u;
+  const bool small = tiled && (tflags & 2u) != 0u;   // 2 x 2 pieces: their kernel runs beside the tiles
   fe_status st = ensure(ctx->tmp_img, ctx->tmp_n, (size_t)w * h, "decode buffer");
   if (st != FE_OK) return st;
   uint8_t* buf[2] = {d_out, ctx->tmp_img};
@@ -686,13 +692,20 @@ fe_status decode_body(fe_ctx* ctx, const fe::DecodeArgs& a, uint32_t iters, cons
   FE_HIP(fe::launch_decode_fill(buf[1 - s0], d_start, w, h, s), "fill");
   FE_HIP(fe::launch_decode_fill(buf[s0], d_start, w, h, s), "fill");
   ctx->last_decode_tiled = tiled;
-  if (tiled && iters) FE_HIP(fe::launch_decode_plan(a, ctx->dec_tiles, ctx->dec_cells, ctx->dec_pieces, s), "plan");
+  uint32_t* small_count = tiled ? ctx->dec_small + n : nullptr;
+  if (tiled && iters) {
+    FE_HIP(fe::launch_zero_u32(small_count, 1, s), "zero 2 x 2 count");
+    FE_HIP(fe::launch_decode_plan(a, ctx->dec_tiles, ctx->dec_cells, ctx->dec_pieces, ctx->dec_small, small_count, s),
+           "plan");
+  }
   for (uint32_t t = 0; t < iters; ++t) {
     Timed tm(ctx, FE_TIMING_DECODE, s);
     const uint8_t* cur = buf[s0 ^ (int)(t & 1u)];
     uint8_t* nxt = buf[s0 ^ (int)((t + 1) & 1u)];
-    if (tiled)
+    if (tiled) {
       FE_HIP(fe::launch_decode_tile_iter(a, ctx->dec_cells, ctx->dec_pieces, cur, nxt, s), "decode launch");
+      if (small) FE_HIP(fe::launch_decode_small(a, ctx->dec_small, small_count, cur, nxt, s), "2 x 2 launch");
+    }
     else
       FE_HIP(fe::launch_decode_iter(a, cur, nxt, s), "decode launch");
   }

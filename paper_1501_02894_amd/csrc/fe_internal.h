@@ -132,17 +132,23 @@ hipError_t launch_decode_fill(uint8_t* dst, const uint8_t* src, uint32_t w, uint
 hipError_t launch_decode_iter(const DecodeArgs& a, const uint8_t* cur, uint8_t* nxt,
                               hipStream_t stream);
 // Tile-ordered decoder: tile_start[t] = first record of top tile t (n at
-// the end); *flag is set when the stream is not tile-ordered with
-// co-centred domains, and the tile kernel must not run then.
+// the end); bit 0 of *flag is set when the stream is not tile-ordered with
+// co-centred domains (the tile kernel must not run then), bit 1 when it has
+// blocks of 2 x 2 pieces (the small-piece kernel must run too).
 hipError_t launch_decode_tile_setup(const DecodeArgs& a, uint32_t* tile_start, uint32_t* flag,
                                     hipStream_t stream);
 // Decode plan (64 x 64-pixel blocks): per block 256 cell -> piece bytes and
-// 256 piece slots of 8 bytes, built once per call from tile_start.
+// 256 piece slots of 8 bytes, built once per call from tile_start; the
+// transforms of 2 x 2 pieces go to small_list (count in *small_count, which
+// the caller zeroes; at most n entries).
 size_t decode_plan_blocks(uint32_t w, uint32_t h);
 hipError_t launch_decode_plan(const DecodeArgs& a, const uint32_t* tile_start, uint8_t* cells, uint2* pieces,
-                              hipStream_t stream);
+                              uint32_t* small_list, uint32_t* small_count, hipStream_t stream);
 hipError_t launch_decode_tile_iter(const DecodeArgs& a, const uint8_t* cells, const uint2* pieces,
                                    const uint8_t* cur, uint8_t* nxt, hipStream_t stream);
+// One iteration of the listed 2 x 2 pieces (after the plan).
+hipError_t launch_decode_small(const DecodeArgs& a, const uint32_t* small_list, const uint32_t* small_count,
+                               const uint8_t* cur, uint8_t* nxt, hipStream_t stream);
 
 // Bitstream packing (Sec. 3.3, 3.4): chunk_bits / chunk_base hold
 // pack_chunks(n) words (at least one), *total receives the stream length in

@@ -5,8 +5,7 @@ The encoder for b_min = 2 (the fused kernel down to 4 x 4, then the 2 x 2
 level with domain means formed from pixels at either phase) must give the
 oracle's stream byte for byte, alone, in a batch and replayed as a plan; both
 decoders, zoom decoding and the compressed file must take such streams (the
-tile decoder steps aside for blocks under 4 x 4, and takes them again once a
-zoom has made them 4 x 4 or larger)."""
+tile decoder with its 2 x 2 pieces decoded by a kernel of their own)."""
 import sys
 
 import numpy as np
@@ -117,9 +116,14 @@ def test_decode_random(torch_dev, ctx, W, H, bm, seed):
     start = np.random.default_rng(seed).integers(0, 256, (H, W)).astype(np.uint8)
     t = _t(torch_dev, rec)
     want = odec.decode(rec, W, H, bm, 3, start=start)
-    got = ctx.decode(t, W, H, bm, 3, start=dev(torch_dev, start)).cpu().numpy()
-    assert ctx.decode_last() == fb.FE_DECODE_RECORDS
-    np.testing.assert_array_equal(got, want)
+    try:
+        for mode, used in ((fb.FE_DECODE_AUTO, fb.FE_DECODE_TILES), (fb.FE_DECODE_RECORDS, fb.FE_DECODE_RECORDS)):
+            ctx.decode_mode(mode)
+            got = ctx.decode(t, W, H, bm, 3, start=dev(torch_dev, start)).cpu().numpy()
+            assert ctx.decode_last() == used
+            np.testing.assert_array_equal(got, want)
+    finally:
+        ctx.decode_mode(fb.FE_DECODE_AUTO)
 
 
 def test_decode_encoded(torch_dev, ctx):
@@ -127,6 +131,7 @@ def test_decode_encoded(torch_dev, ctx):
     img = synth.workload("c2")
     rec = mns.encode(img, 16, 2, [300, 200, 100])
     got = ctx.decode(_t(torch_dev, rec), 512, 512, 16, 8).cpu().numpy()
+    assert ctx.decode_last() == fb.FE_DECODE_TILES
     np.testing.assert_array_equal(got, odec.decode(rec, 512, 512, 16, 8))
 
 
