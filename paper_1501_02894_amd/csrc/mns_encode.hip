@@ -8,9 +8,10 @@
 //      are read once from HBM into LDS; the 2 x 2 round-half-up mean image
 //      H0 of that region and its transpose are formed in LDS on the fly
 //      (Sec. 3, the four-neighbour mean filter).
-//   2. per level l (B = B_max >> (l-1)), each wave runs one pass over its
-//      own list of ranges, a team of T lanes per range (T chosen so the list
-//      fills the wave): the team sums packed-u8 dot products (v_dot4_u32_u8)
+//   2. per level l (B = B_max >> (l-1)), the workgroup's list of ranges is
+//      cut into passes of 64 lanes, a team of T lanes per range, and the
+//      passes are dealt round the four waves: the team sums packed-u8 dot
+//      products (v_dot4_u32_u8)
 //      over row pairs of the range and of the domain window / its transpose,
 //      giving Sum r, Sum r^2, Sum d, Sum d^2 and the 8 isometric Sum r T_e(d);
 //      a DPP butterfly leaves the totals in every lane, and every lane fits
@@ -20,8 +21,9 @@
 //      children, which are exactly the level-l ranges just computed.
 //   4. accepted ranges are written as 16-byte records into per-tile slots
 //      indexed by the Morton code of their top-left B_min cell; failed ranges
-//      are compacted (wave ballot + prefix) into the parent list and their
-//      four children into the next level's list.
+//      are compacted (wave ballot + prefix, one LDS atomic per pass) into the
+//      workgroup's parent list and their four children into the next level's
+//      list, which every wave reads after a barrier.
 //
 // After the workgroup finishes, its tiles' occupancy masks are published;
 // the ordering kernels (order.hip) pack the records into the depth-first
@@ -55,7 +57,7 @@ struct Geo {
   static constexpr int HH4 = (HH + 3) & ~3;                   // H0 rows, multiple of 4
   static constexpr int H0_W = HH4 * HP / 4 + 4;
   static constexpr int H0T_W = HW * TP / 4 + 4;
-  static_assert(NT % 4 == 0, "tiles per workgroup must split over 4 waves");
+  static_assert(NT % 4 == 0 && NT <= 256, "tiles per workgroup: a multiple of 4, at most one per lane");
 };
 
 struct Region {
@@ -95,16 +97,6 @@ __device__ __forceinline__ int morton(uint32_t meta) {
     code |= ((cy >> bit) & 1) << (2 * bit + 1);
   }
   return code;
-}
-
-// Make this wave's LDS writes visible to its own later reads (the lanes of
-// one wave exchange data through LDS; no other wave is involved).  The
-// fences are restricted to LDS so that outstanding global stores (records)
-// are not waited for.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Geometry of one block of top tiles and of its staged region.
@@ -248,25 +240,69 @@ struct Lds {
   uint32_t img[G::IMG_W];
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
-  uint32_t meta[4][2][G::CAPW];    // per wave: range lists of two consecutive levels
-  uint32_t par[4][2][G::PCAPW];    // per wave: their parents, meta | m << 24
+  uint32_t meta[2][4 * G::CAPW];   // the block's range lists of two consecutive levels
+  uint32_t par[2][4 * G::PCAPW];   // their parents, meta | m << 24
+  uint32_t cnt[L + 1];             // per level: ranges that failed (parents of the next list)
   unsigned long long mask[G::NT];
 };
 
 // Lane `src` of the wave's value v.
 __device__ __forceinline__ int lane_read(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
 
-// The quadtree of one block, each wave on its own tiles.  Uses only LDS
-// data staged for the block; writes records to staging and tile masks.
+// VALU instructions of one level pass of the compiled kernel by range side:
+// per moment iteration (one row pair of a range per lane) and per pass (the
+// fits, phase 2, record stores and compaction, whatever T is).
+template <int BB>
+struct PassCost;
+template <>
+struct PassCost<32> { static constexpr int it = 250, pass = 220; };
+template <>
+struct PassCost<16> { static constexpr int it = 127, pass = 200; };
+template <>
+struct PassCost<8> { static constexpr int it = 79, pass = 300; };
+template <>
+struct PassCost<4> { static constexpr int it = 49, pass = 280; };
+
+// Team size T (lanes per range, a power of two up to min(BB/2, 16)) for a
+// workgroup list of n ranges of side BB.  The top level splits its tiles
+// evenly over the four waves and fills their lanes.  Lower levels take the T
+// of least VALU work in total, ceil(n T / 64) passes of ceil(BB / 2T)
+// moment iterations plus the per-pass work: small teams when the list is
+// long, large ones when a short list would otherwise leave lanes idle.
+template <int BB>
+__device__ __forceinline__ int team_size(int n, bool top) {
+  constexpr int TMAX = BB / 2 < 16 ? BB / 2 : 16;
+  if (top) {
+    const int nw = (n + 3) >> 2;
+    int T = 1;
+    while (T < TMAX && nw * T * 2 <= 64) T *= 2;
+    return T;
+  }
+  int best_t = 1, best = 0x7fffffff;
+  for (int T = 1, lg = 0; T <= TMAX; T *= 2, ++lg) {
+    const int c = ((n * T + 63) >> 6) * ((BB / 2 + T - 1) / T * PassCost<BB>::it + PassCost<BB>::pass + 12 * lg);
+    if (c < best) {
+      best = c;
+      best_t = T;
+    }
+  }
+  return best_t;
+}
+
+// The quadtree of one block, the four waves sharing each level's list.  Uses
+// only LDS data staged for the block; writes records to staging and tile
+// masks.
 //
-// One pass per level over the wave's list of ranges, a team of T lanes per
-// range: the team accumulates the range's moments and reduces them so that
-// every lane of the team holds the totals; every lane then fits the range.
-// From level 2 on the list holds the four children (Z order) of each range
-// that failed the level above, in consecutive teams, so the same pass also
-// runs the parent's phase 2 (Technique 1) across the four teams.  Accepted
-// ranges are written at once; failed ones are compacted (ballot prefix) into
-// the next level's parent list and their children into its range list.
+// Per level the list is cut into passes of 64 lanes, a team of T lanes per
+// range, and pass p goes to wave (p + rot) mod 4: the team accumulates the
+// range's moments and reduces them so that every lane of the team holds the
+// totals; every lane then fits the range.  From level 2 on the list holds
+// the four children (Z order) of each range that failed the level above, in
+// consecutive teams of one pass (4T divides 64), so the same pass also runs
+// the parent's phase 2 (Technique 1) across the four teams.  Accepted ranges
+// are written at once; failed ones are compacted (ballot prefix, one LDS
+// atomic per pass) into the next level's parent list and their children
+// into its range list.  A barrier ends each level.
 // Record slot of Morton cell `cell` of tile t (row-major in a block of GX
 // tiles per row) inside its block: one row of the block's tiles at a time,
 // and inside a row cell-major, so that the records of one cell of a tile
@@ -278,7 +314,8 @@ __device__ __forceinline__ uint32_t rec_slot(uint32_t t, int cell, int cells) {
 }
 
 template <int BMAX, int L, int GX, int GY, bool EXT>
-__device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm) {
+__device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm,
+                                              uint32_t rot) {
   using G = Geo<BMAX, L, GX, GY>;
   // record cells per tile: B_min cells, or 2 x 2 cells when the tree goes on
   // to 2 x 2 (EXT), whose Morton codes are those of the B_min cells times 4
@@ -293,38 +330,29 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   unsigned long long* s_mask = sm.mask;
   const uint64_t slot0 = (uint64_t)bg.sblk * (uint64_t)(G::NT * CE);   // the block's record slots
   const int wave = tid >> 6, lane = tid & 63;
-  const int t_first = wave * G::NTW;
-  uint32_t* w_meta0 = sm.meta[wave][0];
-  uint32_t* w_meta1 = sm.meta[wave][1];
-  // this wave's tiles of the block that lie inside the image
-  const int my_t = t_first + lane;
-  const bool my_valid = lane < G::NTW && (my_t & (GX - 1)) < gx && (my_t >> G::LOG_GX) < gy;
-  const uint64_t vbal = __ballot(my_valid);
-  if (vbal == 0) return;   // this wave has no tile of the block inside the image
-  if (my_valid)
-    w_meta0[__builtin_amdgcn_mbcnt_hi((uint32_t)(vbal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vbal, 0u))] =
-        (uint32_t)my_t << 16;
-  wave_sync();
+  const int p0 = (wave - (int)rot) & 3;   // this wave's first pass of a level
 
-  int n = (int)__popcll(vbal);  // ranges in the current list (wave-uniform)
+  // ranges in the current list (workgroup-uniform); level 1: the block's
+  // tiles inside the image, listed by the kernel before its barrier
+  int n = gx * gy;
   for (int lev = 1; lev <= L; ++lev) {
-    const uint32_t* cur = (lev & 1) ? w_meta0 : w_meta1;
-    uint32_t* nxt = (lev & 1) ? w_meta1 : w_meta0;
-    const uint32_t* ppar = sm.par[wave][(lev - 1) & 1];   // parents of `cur` (level lev-1)
-    uint32_t* npar = sm.par[wave][lev & 1];               // parents of `nxt`
+    const uint32_t* cur = sm.meta[(lev - 1) & 1];
+    uint32_t* nxt = sm.meta[lev & 1];
+    const uint32_t* ppar = sm.par[(lev - 1) & 1];   // parents of `cur` (level lev-1)
+    uint32_t* npar = sm.par[lev & 1];               // parents of `nxt`
+    uint32_t* nfail = &sm.cnt[lev];                 // zeroed by the kernel
     const bool last = lev == L && !EXT;   // EXT: the 4 x 4 level is tested too
     const uint32_t thr = last ? 0u : a.thr[lev - 1];
     const int B = BMAX >> (lev - 1);
-    uint32_t nfail = 0;
 
     auto level_pass = [&](auto bconst) {
       constexpr int BB = decltype(bconst)::value;
       constexpr bool ALIGNED = BB >= 16;
-      int T = 1;
-      while (T < BB / 2 && T < 16 && n * (T * 2) <= 64) T *= 2;
+      const int T = team_size<BB>(n, BB == BMAX);
       const int logT = __builtin_ctz((unsigned)T);
-      for (int base = 0; base < n * T; base += 64) {
-        const int idx = base + lane;
+      const int passes = (n * T + 63) >> 6;
+      for (int p = p0; p < passes; p += 4) {
+        const int idx = p * 64 + lane;
         const int e = idx >> logT, t = idx & (T - 1);
         const bool valid = e < n;
         // ---- moments of range e (the team's rows t, t + T, ...)
@@ -437,31 +465,37 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             continue;
           }
         }
-        if (fail) {
-          const uint32_t q = nfail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          npar[q] = meta | ((fit & 0xffu) << 24);
-          const uint32_t half = (uint32_t)(BB / 2 / G::BMIN);
-          const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
+        if (bal) {
+          const int first = (int)__builtin_ctzll(bal);
+          uint32_t q0 = 0;
+          if (lane == first) q0 = atomicAdd(nfail, (uint32_t)__popcll(bal));
+          q0 = (uint32_t)__shfl((int)q0, first);
+          if (fail) {
+            const uint32_t q = q0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            npar[q] = meta | ((fit & 0xffu) << 24);
+            const uint32_t half = (uint32_t)(BB / 2 / G::BMIN);
+            const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
 #pragma unroll
-          for (uint32_t ch = 0; ch < 4; ++ch)
-            nxt[4 * q + ch] = tile | ((cy + (ch >> 1) * half) << 8) | (cx + (ch & 1u) * half);
+            for (uint32_t ch = 0; ch < 4; ++ch)
+              nxt[4 * q + ch] = tile | ((cy + (ch >> 1) * half) << 8) | (cx + (ch & 1u) * half);
+          }
         }
-        nfail += (uint32_t)__popcll(bal);
       }
     };
     if constexpr (BMAX >= 32) { if (B == 32) level_pass(std::integral_constant<int, 32>{}); }
     if constexpr (BMAX >= 16 && G::BMIN <= 16) { if (B == 16) level_pass(std::integral_constant<int, 16>{}); }
     if constexpr (BMAX >= 8 && G::BMIN <= 8) { if (B == 8) level_pass(std::integral_constant<int, 8>{}); }
     if constexpr (G::BMIN <= 4) { if (B == 4) level_pass(std::integral_constant<int, 4>{}); }
-    wave_sync();
-    n = (int)(4 * nfail);
+    __syncthreads();   // the next list, its parents and count are complete
+    n = (int)(4u * *nfail);
     if (last || n == 0) break;
   }
 
-  // ---- publish the wave's tiles' occupancy masks
-  wave_sync();
-  if (my_valid) a.masks[tile_global<G::LOG_GX>((uint32_t)my_t << 16, rg)] = s_mask[my_t];
+  // ---- publish the block's tiles' occupancy masks (complete after the
+  // barrier that ended the last level)
+  for (int t = tid; t < G::NT; t += 256)
+    if ((t & (GX - 1)) < gx && (t >> G::LOG_GX) < gy) a.masks[tile_global<G::LOG_GX>((uint32_t)t << 16, rg)] = s_mask[t];
 }
 
 template <int BMAX, int L, int GX, int GY, bool EXT>
@@ -476,8 +510,11 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   const BlockGeo bg = block_geo<BMAX, GX, GY>(a.blocks[wg]);
   Stage<G>::run(bg, tid, sm.img, sm.h0, sm.h0t);
   for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
+  if (tid <= L) sm.cnt[tid] = 0u;
+  // level-1 list: the block's tiles inside the image, row-major (gx gy <= NT <= 256)
+  if (tid < bg.gx * bg.gy) sm.meta[0][tid] = (uint32_t)((tid / bg.gx) * GX + tid % bg.gx) << 16;
   __syncthreads();
-  process_block<BMAX, L, GX, GY, EXT>(a, bg, sm);
+  process_block<BMAX, L, GX, GY, EXT>(a, bg, sm, wg & 3u);
 }
 
 // One lane per logical workgroup: find its image (binary search over the
