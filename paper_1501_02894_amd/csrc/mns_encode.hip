@@ -22,8 +22,8 @@
 //   4. accepted ranges are written as 16-byte records into per-tile slots
 //      indexed by the Morton code of their top-left B_min cell; failed ranges
 //      are compacted (wave ballot + prefix, one LDS atomic per pass) into the
-//      workgroup's parent list and their four children into the next level's
-//      list, which every wave reads after a barrier.
+//      workgroup's parent list, which every wave reads after a barrier: entry
+//      e of the next level is child e mod 4 (Z order) of parent e / 4.
 //
 // After the workgroup finishes, its tiles' occupancy masks are published;
 // the ordering kernels (order.hip) pack the records into the depth-first
@@ -240,8 +240,8 @@ struct Lds {
   uint32_t img[G::IMG_W];
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
-  uint32_t meta[2][4 * G::CAPW];   // the block's range lists of two consecutive levels
-  uint32_t par[2][4 * G::PCAPW];   // their parents, meta | m << 24
+  uint32_t top[G::NT];             // level-1 list: the block's tiles inside the image
+  uint32_t par[2][4 * G::PCAPW];   // failed ranges of two consecutive levels, meta | m << 24
   uint32_t cnt[L + 1];             // per level: ranges that failed (parents of the next list)
   unsigned long long mask[G::NT];
 };
@@ -301,8 +301,8 @@ __device__ __forceinline__ int team_size(int n, bool top) {
 // consecutive teams of one pass (4T divides 64), so the same pass also runs
 // the parent's phase 2 (Technique 1) across the four teams.  Accepted ranges
 // are written at once; failed ones are compacted (ballot prefix, one LDS
-// atomic per pass) into the next level's parent list and their children
-// into its range list.  A barrier ends each level.
+// atomic per pass) into the parent list of the next level, whose entry e is
+// then child e mod 4 of parent e / 4.  A barrier ends each level.
 // Record slot of Morton cell `cell` of tile t (row-major in a block of GX
 // tiles per row) inside its block: one row of the block's tiles at a time,
 // and inside a row cell-major, so that the records of one cell of a tile
@@ -336,10 +336,8 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   // tiles inside the image, listed by the kernel before its barrier
   int n = gx * gy;
   for (int lev = 1; lev <= L; ++lev) {
-    const uint32_t* cur = sm.meta[(lev - 1) & 1];
-    uint32_t* nxt = sm.meta[lev & 1];
-    const uint32_t* ppar = sm.par[(lev - 1) & 1];   // parents of `cur` (level lev-1)
-    uint32_t* npar = sm.par[lev & 1];               // parents of `nxt`
+    const uint32_t* ppar = sm.par[(lev - 1) & 1];   // parents of this level's ranges
+    uint32_t* npar = sm.par[lev & 1];               // this level's failed ranges
     uint32_t* nfail = &sm.cnt[lev];                 // zeroed by the kernel
     const bool last = lev == L && !EXT;   // EXT: the 4 x 4 level is tested too
     const uint32_t thr = last ? 0u : a.thr[lev - 1];
@@ -359,10 +357,18 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
         uint32_t acc[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] = 0u;
-        uint32_t meta = 0;
+        uint32_t meta = 0, pe = 0;
         int X = 0, Y = 0;
         if (valid) {
-          meta = cur[e];
+          if constexpr (BB == BMAX) {
+            meta = sm.top[e];
+          } else {
+            // child e mod 4 (Z order) of the failed parent e / 4
+            constexpr uint32_t side = (uint32_t)(BB / G::BMIN);   // in B_min cells
+            pe = ppar[e >> 2];
+            const uint32_t c = (uint32_t)e & 3u;
+            meta = (pe & 0x00ff0000u) | ((((pe >> 8) & 0xffu) + (c >> 1) * side) << 8) | ((pe & 0xffu) + (c & 1u) * side);
+          }
           range_xy<BMAX, G::BMIN, G::LOG_GX>(meta, rg, X, Y);
           const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
           const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
@@ -390,7 +396,6 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
             const double thr2 = (400.0 * NB * NB) * (double)a.thr[lev - 2];
             const int c = e & 3;
             const int g0 = lane - c * T;               // lane of child 0 (same t)
-            const uint32_t pe = valid ? ppar[e >> 2] : 0u;
             const int m = (int)(pe >> 24);
             int O = (int)((2u * acc[0] + (uint32_t)(BB * BB)) >> (LOGNB + 1));
             const int O0 = lane_read(O, g0), O1 = lane_read(O, g0 + T), O2 = lane_read(O, g0 + 2 * T);
@@ -470,16 +475,9 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
           uint32_t q0 = 0;
           if (lane == first) q0 = atomicAdd(nfail, (uint32_t)__popcll(bal));
           q0 = (uint32_t)__shfl((int)q0, first);
-          if (fail) {
-            const uint32_t q = q0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            npar[q] = meta | ((fit & 0xffu) << 24);
-            const uint32_t half = (uint32_t)(BB / 2 / G::BMIN);
-            const uint32_t cx = meta & 0xffu, cy = (meta >> 8) & 0xffu, tile = meta & 0xffff0000u;
-#pragma unroll
-            for (uint32_t ch = 0; ch < 4; ++ch)
-              nxt[4 * q + ch] = tile | ((cy + (ch >> 1) * half) << 8) | (cx + (ch & 1u) * half);
-          }
+          if (fail)
+            npar[q0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
+                meta | ((fit & 0xffu) << 24);
         }
       }
     };
@@ -487,7 +485,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
     if constexpr (BMAX >= 16 && G::BMIN <= 16) { if (B == 16) level_pass(std::integral_constant<int, 16>{}); }
     if constexpr (BMAX >= 8 && G::BMIN <= 8) { if (B == 8) level_pass(std::integral_constant<int, 8>{}); }
     if constexpr (G::BMIN <= 4) { if (B == 4) level_pass(std::integral_constant<int, 4>{}); }
-    __syncthreads();   // the next list, its parents and count are complete
+    __syncthreads();   // the next level's parents and their count are complete
     n = (int)(4u * *nfail);
     if (last || n == 0) break;
   }
@@ -512,7 +510,7 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
   if (tid <= L) sm.cnt[tid] = 0u;
   // level-1 list: the block's tiles inside the image, row-major (gx gy <= NT <= 256)
-  if (tid < bg.gx * bg.gy) sm.meta[0][tid] = (uint32_t)((tid / bg.gx) * GX + tid % bg.gx) << 16;
+  if (tid < bg.gx * bg.gy) sm.top[tid] = (uint32_t)((tid / bg.gx) * GX + tid % bg.gx) << 16;
   __syncthreads();
   process_block<BMAX, L, GX, GY, EXT>(a, bg, sm, wg & 3u);
 }
