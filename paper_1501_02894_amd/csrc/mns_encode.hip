@@ -42,10 +42,9 @@ struct Geo {
   static constexpr int BMIN = BMAX >> (L - 1);
   static constexpr int NT = GX * GY;                          // tiles per workgroup
   static constexpr int LOG_GX = Log2<GX>::value;
-  static constexpr int NTW = NT / 4;                          // tiles per wave
   static constexpr int CELLS = 1 << (2 * (L - 1));
-  static constexpr int CAPW = NTW * CELLS;                    // per-wave deepest list bound
-  static constexpr int PCAPW = CAPW / 4 > 0 ? CAPW / 4 : 1;   // per-wave parent list bound
+  // failed ranges of one level, at most NT 4^(L-2) (level L-1)
+  static constexpr int PCAP = NT * CELLS / 4 > 0 ? NT * CELLS / 4 : 1;
   static constexpr int TW = GX * BMAX, TH = GY * BMAX;        // tile block in pixels
   static constexpr int TPITCH = TW + 4;                       // tile pixel row pitch (bytes)
   static constexpr int RWA = ((GX + 1) * BMAX + 6 + 7) & ~7;  // region width bound (px)
@@ -241,7 +240,7 @@ struct Lds {
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
   uint32_t top[G::NT];             // level-1 list: the block's tiles inside the image
-  uint32_t par[2][4 * G::PCAPW];   // failed ranges of two consecutive levels, meta | m << 24
+  uint32_t par[2][G::PCAP];        // failed ranges of two consecutive levels, meta | m << 24
   uint32_t cnt[L + 1];             // per level: ranges that failed (parents of the next list)
   unsigned long long mask[G::NT];
 };
