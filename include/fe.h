@@ -194,8 +194,8 @@ fe_status fe_create(int device, fe_ctx** out);
 void fe_destroy(fe_ctx* ctx);
 
 /*
- * Domain pyramid level used by no-search (Sec. 3: "mean filter to four
- * neighbor pixels"): d_out[j * (W/2) + i] = (I[2j][2i] + I[2j][2i+1] +
+ * Domain pyramid level used by no-search (Sec. 3: each domain pixel is the
+ * mean of a 2 x 2 pixel group): d_out[j * (W/2) + i] = (I[2j][2i] + I[2j][2i+1] +
  * I[2j+1][2i] + I[2j+1][2i+1] + 2) >> 2, a dense (H/2) x (W/2) uint8 image.
  * W and H even and >= 2; stride >= W, multiple of 4; d_img 4-byte aligned.
  */

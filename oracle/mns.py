@@ -254,8 +254,8 @@ def quantised_mean(sr, n: int):
 
 def fit_phase1(mom: dict, n: int):
     """Best (isometry e, contrast k/8) and luminance m of each range, and the
-    scaled collage error S = 64 n E (Sec. 3: "find the best value for the
-    contrast factor and calculate the error").
+    scaled collage error S = 64 n E (Sec. 3: the no-search coder fits only
+    the contrast to the one domain, then measures the error of that fit).
 
     Every (e, k) is scored; the first minimum in (e, k) order wins.
     """

@@ -26,6 +26,14 @@ def _c1_stream():
     return img, mns.encode(img, 8, 4, [600])
 
 
+def _phase2_pins():
+    g = _golden()
+    pins.test_phase2_mean_difference_at_the_stored_width(g)
+    pins.test_phase2_threshold_is_strict_at_the_worst_child(g)
+    # a stream rich in phase 2: C2, 16 -> 4, every failed range decided by definition
+    pins.test_phase2_decisions_by_definition(g, "c2", 16, 4, [300, 200])
+
+
 # the pins, cheapest first; each is a zero-argument callable
 PINS = [
     ("paper constants", lambda: pins.test_paper_constants(_golden())),
@@ -40,6 +48,7 @@ PINS = [
     ("flat", pins.test_flat_image),
     ("decode step", lambda: pins.test_decoder_one_step_by_definition(_c1_stream())),
     ("stream c1", lambda: pins.test_stream_structure_and_decisions("c1", 8, 4, [600])),
+    ("phase 2 by definition", _phase2_pins),
     ("full search tiny", pins.test_fullsearch_bruteforce_tiny),
 ]
 
@@ -161,6 +170,41 @@ def _all_domains_floor(img, B):
     return np.ascontiguousarray(win).reshape(-1, B * B)
 
 
+def _fit2_factory(thr_minus=0, thr_scale=1, strict_delta=False):
+    """Technique 1 with one plausible slip in its rejection rule."""
+    def fit2(I, h0, xs, ys, B, level, m, t):
+        b = B // 2
+        nb = b * b
+        c1, c2 = mns.PHASE2_SETS[level]
+        delta = mns.PHASE2_DELTA[level]
+        m = np.asarray(m, np.int64)
+        cx, cy = mns.children_xy(xs, ys, B)
+        mom = [mns.range_moments(I, h0, cx[:, c], cy[:, c], b) for c in range(4)]
+        O = np.zeros((m.size, 4), np.int64)
+        for c in range(3):
+            O[:, c] = mns.quantised_mean(mom[c]["sr"], nb)
+        O[:, 3] = 4 * m - O[:, 0] - O[:, 1] - O[:, 2]
+        dev = np.abs(O - m[:, None])
+        accept = np.all(dev < delta if strict_delta else dev <= delta, axis=1)
+        accept &= (O[:, 3] >= 0) & (O[:, 3] <= 255)
+        bits = np.zeros(m.size, np.int64)
+        S = np.zeros((m.size, 4), np.int64)
+        tt = (int(t) - thr_minus) * thr_scale
+        for c in range(4):
+            mc = mom[c]
+            Q = nb * mc["sdd"] - mc["sd"] * mc["sd"]
+            Rr = nb * mc["srr"] - mc["sr"] * mc["sr"]
+            P = nb * mc["srd"][:, 0] - mc["sr"] * mc["sd"]
+            f1 = c1 * c1 * Q - 40 * c1 * P
+            f2 = c2 * c2 * Q - 40 * c2 * P
+            use2 = f2 < f1
+            S[:, c] = np.where(use2, f2, f1) + 400 * Rr + 400 * (nb * O[:, c] - mc["sr"]) ** 2
+            bits |= use2.astype(np.int64) << c
+            accept &= S[:, c] < 400 * nb * nb * tt
+        return accept, O, bits, S
+    return fit2
+
+
 MUTANTS = {
     "downsample rounds down": (mns, "downsample", _downsample_floor),
     "domain centred at x - B": (mns, "domain_origin", _domain_wrong_centre),
@@ -177,6 +221,9 @@ MUTANTS = {
     "Morton x bit above y": (mns, "stream_key", _key_swapped),
     "phase-2 set typo": (mns, "PHASE2_SETS", {1: (4, 10), 2: (8, 14), 3: (10, 18)}),
     "phase-2 bound off by one": (mns, "PHASE2_DELTA", {1: 16, 2: 32, 3: 32}),
+    "phase-2 threshold t - 1": (mns, "fit_phase2", _fit2_factory(thr_minus=1)),
+    "phase-2 threshold 0.9 t": (mns, "fit_phase2", _fit2_factory(thr_scale=0.9)),
+    "phase-2 strict bound on the mean difference": (mns, "fit_phase2", _fit2_factory(strict_delta=True)),
     "decoder 2x2 mean rounds down": (decode, "_domain_blocks", _decode_floor),
     "full search: k rounds down": (fullsearch, "closed_form_k", _closed_k_floor),
     "full search: domains round down": (fullsearch, "all_domains", _all_domains_floor),

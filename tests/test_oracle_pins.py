@@ -359,7 +359,9 @@ def test_stream_structure_and_decisions(name, b_max, b_min, thr):
             err = sum((s * (int(d[i, j]) - dbar) + O[c] - int(child[i, j])) ** 2
                       for i in range(b) for j in range(b))
             assert err / (b * b) < thr[lvl - 1]
-    # every split range failed both phases (pixelwise check of phase 1)
+    # every split range failed phase 1 (pixelwise check of the fit it took;
+    # its phase-2 rejection is checked by definition in
+    # test_phase2_decisions_by_definition)
     for info in trace[:-1]:
         B = info["B"]
         split = ~info["accept1"]
@@ -374,6 +376,176 @@ def test_stream_structure_and_decisions(name, b_max, b_min, thr):
             probe["dy"] = mns.domain_origin(y, B, H)
             probe["iso"], probe["s_idx"], probe["lum"] = info["e"][idx], info["k"][idx], info["m"][idx]
             assert _pixel_mse_phase1(I, probe, B) >= thr[info["level"] - 1]
+
+
+def _phase2_by_definition(I, xs, ys, B, level, m, t, golden):
+    """Technique 1 (Sec. 3.1-3.3) decided from the pixels and the paper's
+    printed constants, for parents at (xs, ys) of side B whose phase-1 mean
+    is m.  Returns (accept, admissible, O, err): O[:, c] the child means with
+    O[:, 3] from eq. (1), err[:, c] = 400 nb^2 E_c of the better contrast of
+    the level's set, E_c the child's pixelwise collage error.
+
+    Child c (Z order) is fitted to its own co-centred domain, each 2 x 2
+    group averaged and rounded half up.  With s = c'/20 and mean O,
+    20 nb (r^_p - r_p) = c' (nb d_p - Sum d) + 20 nb (O - r_p), an integer,
+    so 400 nb^2 E_c is the exact sum of its squares and
+    MSE < t  <=>  400 nb^2 E_c < 400 nb^3 t.  The means round half up as
+    floor(mean + 1/2), exact here because nb is a power of two."""
+    H, W = I.shape
+    b = B // 2
+    nb = b * b
+    cs = [Fraction(str(v)) * 20 for v in golden["phase2_contrast_sets"]["values"][str(level)]]
+    assert all(c.denominator == 1 for c in cs)
+    cs = [int(c) for c in cs]
+    M = golden["phase2_mean_bits"]["values"][str(level)]
+    bound = 2 ** (M - 1) - 1          # M bits, one of them the sign
+    xs, ys, m = (np.asarray(v, np.int64) for v in (xs, ys, m))
+    ii, jj = np.arange(b), np.arange(2 * b)
+    O = np.zeros((xs.size, 4), np.int64)
+    err = np.zeros((xs.size, 4), np.int64)
+    for c, (ox, oy) in enumerate(((0, 0), (b, 0), (0, b), (b, b))):
+        cx, cy = xs + ox, ys + oy
+        r = I[cy[:, None, None] + ii[None, :, None], cx[:, None, None] + ii[None, None, :]]
+        dx = np.clip(cx - b // 2, 0, W - 2 * b)
+        dy = np.clip(cy - b // 2, 0, H - 2 * b)
+        big = I[dy[:, None, None] + jj[None, :, None], dx[:, None, None] + jj[None, None, :]]
+        d = (big[:, 0::2, 0::2] + big[:, 0::2, 1::2] + big[:, 1::2, 0::2] + big[:, 1::2, 1::2] + 2) // 4
+        if c < 3:
+            O[:, c] = np.floor(r.sum(axis=(1, 2)) / nb + 0.5).astype(np.int64)
+        else:
+            O[:, 3] = 4 * m - O[:, 0] - O[:, 1] - O[:, 2]          # eq. (1)
+        sd = d.sum(axis=(1, 2))
+        e = [((cc * (nb * d - sd[:, None, None]) + 20 * nb * (O[:, c][:, None, None] - r)) ** 2).sum(axis=(1, 2))
+             for cc in cs]
+        err[:, c] = np.minimum(e[0], e[1])
+    adm = np.all(np.abs(O - m[:, None]) <= bound, axis=1) & (O[:, 3] >= 0) & (O[:, 3] <= 255)
+    ok = adm & np.all(err < 400 * nb ** 3 * int(t), axis=1)
+    return ok, adm, O, err
+
+
+def _child_mse_fraction(I, x, y, B, c, O, s):
+    """Pixelwise MSE of child c of the parent at (x, y) with contrast s and
+    mean O, in rationals (the definition the scaled integers stand for)."""
+    H, W = I.shape
+    b = B // 2
+    cx, cy = x + (c % 2) * b, y + (c // 2) * b
+    child = I[cy:cy + b, cx:cx + b]
+    dx, dy = min(max(cx - b // 2, 0), W - 2 * b), min(max(cy - b // 2, 0), H - 2 * b)
+    big = I[dy:dy + 2 * b, dx:dx + 2 * b]
+    d = [[Fraction(int(big[2 * i:2 * i + 2, 2 * j:2 * j + 2].sum()), 4) for j in range(b)] for i in range(b)]
+    d = [[int(v + Fraction(1, 2)) for v in row] for row in d]
+    dbar = Fraction(sum(map(sum, d)), b * b)
+    return sum((s * (d[i][j] - dbar) + O - int(child[i, j])) ** 2 for i in range(b) for j in range(b)) / (b * b)
+
+
+PHASE2_STREAMS = [
+    ("c1", 8, 4, [600]),
+    ("c2", 16, 4, [300, 200]),
+    ("c2", 16, 4, [40, 20]),
+    ("c2", 16, 2, [300, 200, 100]),     # the paper's four levels, 16 x 16 to 2 x 2
+]
+
+
+@pytest.mark.parametrize("name,b_max,b_min,thr", PHASE2_STREAMS)
+def test_phase2_decisions_by_definition(golden, name, b_max, b_min, thr):
+    """Every range that fails phase 1 above the last level is stored by
+    Technique 1 exactly when the definition says so: all four child means
+    (O_4 by eq. (1), inside 0..255) within the stored M-bit signed width of
+    the parent mean, and every child's MSE under the better contrast of the
+    level's set below t_l (Sec. 3.1-3.3).  Rejections are checked as well as
+    acceptances, and the boundary cases the streams reach (a difference at
+    the bound, a worst child MSE within one grey level squared of t_l) are
+    required to occur, so a stricter rule cannot pass."""
+    img = synth.workload(name)
+    I = img.astype(np.int64)
+    trace = []
+    rec = mns.encode(img, b_max, b_min, thr, trace=trace)
+    reach = {"delta at bound": False, "worst MSE in [t-1, t)": False, "rejected on MSE alone": False}
+    for info in trace[:-1]:
+        lvl, B = info["level"], info["B"]
+        t = thr[lvl - 1]
+        fail = ~info["accept1"]
+        xs, ys, m = info["x"][fail], info["y"][fail], info["m"][fail]
+        ok, adm, O, err = _phase2_by_definition(I, xs, ys, B, lvl, m, t, golden)
+        np.testing.assert_array_equal(info["accept2"], ok, err_msg=f"level {lvl}")
+        nb = (B // 2) ** 2
+        np.testing.assert_array_equal(info["O"], O)
+        # the oracle's scaled errors are the chosen contrast's: the better one
+        np.testing.assert_array_equal(info["S2"] * nb, err)
+        bound = 2 ** (golden["phase2_mean_bits"]["values"][str(lvl)] - 1) - 1
+        worst = err.max(axis=1)
+        near = adm & (worst >= 400 * nb ** 3 * (t - 1)) & (worst < 400 * nb ** 3 * t)
+        reach["delta at bound"] |= bool(np.any(ok & np.any(np.abs(O - m[:, None]) == bound, axis=1)))
+        reach["worst MSE in [t-1, t)"] |= bool(near.any())
+        reach["rejected on MSE alone"] |= bool(np.any(adm & ~ok))
+        # the scaled integers against rational arithmetic, on the ranges
+        # nearest the threshold on either side
+        sets = [Fraction(str(v)) for v in golden["phase2_contrast_sets"]["values"][str(lvl)]]
+        for idx in np.argsort(np.abs(worst - 400 * nb ** 3 * t))[:3]:
+            c = int(np.argmax(err[idx]))
+            mse = min(_child_mse_fraction(I, int(xs[idx]), int(ys[idx]), B, c, int(O[idx, c]), s) for s in sets)
+            assert mse == Fraction(int(err[idx, c]), 400 * nb ** 3)
+    if (name, b_min, thr[0]) in (("c2", 4, 300), ("c2", 2, 300)):
+        assert all(reach.values()), reach
+    assert np.count_nonzero(rec["flags"] & 1) == sum(int(i["accept2"].sum()) for i in trace[:-1])
+
+
+def _flat_blocks(vals, q):
+    """An image of flat q x q blocks with the given grey values (rows of blocks)."""
+    return np.kron(np.asarray(vals, np.int64), np.ones((q, q), np.int64)).astype(np.uint8)
+
+
+def test_phase2_mean_difference_at_the_stored_width(golden):
+    """A parent whose flat children sit at +-2^(M-1)-1 grey levels from its
+    mean is stored by Technique 1; one level further it is split (Sec. 3.1:
+    the means must be close; Sec. 3.3: M-bit signed differences, O_4 from
+    eq. (1)).  8 -> 4 on a 16 x 16 image of flat 4 x 4 blocks: every parent
+    8 x 8 is a checkerboard of its children, m + D, m - D, m - D, m + D, so
+    phase 1 (one contrast for the whole parent) fails a small threshold."""
+    bound = 2 ** (golden["phase2_mean_bits"]["values"]["1"] - 1) - 1
+    m = 120
+    for D, stored in ((bound, True), (bound + 1, False)):
+        v = [[m + D, m - D], [m - D, m + D]]
+        img = _flat_blocks(np.tile(v, (2, 2)), 4)
+        I = img.astype(np.int64)
+        trace = []
+        rec = mns.encode(img, 8, 4, [20], trace=trace)
+        info = trace[0]
+        assert not info["accept1"].any()          # phase 1 fails every parent
+        ok, adm, O, err = _phase2_by_definition(I, info["x"], info["y"], 8, 1, info["m"], 20, golden)
+        assert np.all(np.abs(O - m) == D) and np.all(info["m"] == m)
+        assert ok.all() == stored and adm.all() == stored
+        np.testing.assert_array_equal(info["accept2"], ok)
+        p2 = rec[(rec["flags"] & 1) == 1]
+        assert p2.size == (4 if stored else 0)
+        if stored:
+            assert np.all(np.abs(p2["dlum"].astype(np.int64)) == D)
+
+
+def test_phase2_threshold_is_strict_at_the_worst_child(golden):
+    """Technique 1 stores a parent when every child's MSE is below t_l and
+    splits it when the worst child's MSE reaches t_l (Sec. 3.1), with the
+    threshold placed from the definition at the worst child's error: just
+    above it the parent is stored, at its floor it is split."""
+    img = synth.workload("c2")
+    I = img.astype(np.int64)
+    trace = []
+    mns.encode(img, 16, 4, [300, 200], trace=trace)
+    info = trace[1]                                  # level 2, 8 x 8 parents, 4 x 4 children
+    fail = ~info["accept1"]
+    xs, ys, m = info["x"][fail], info["y"][fail], info["m"][fail]
+    ok, adm, O, err = _phase2_by_definition(I, xs, ys, 8, 2, m, 200, golden)
+    nb = 16
+    worst = err.max(axis=1)
+    # admissible parents whose worst child MSE is not an integer
+    cand = np.flatnonzero(adm & (worst % (400 * nb ** 3) != 0) & (worst < 400 * nb ** 3 * 250))
+    assert cand.size > 0
+    for idx in cand[:5]:
+        mse = Fraction(int(worst[idx]), 400 * nb ** 3)
+        x, y = int(xs[idx]), int(ys[idx])
+        for t, stored in ((int(mse) + 1, True), (int(mse), False)):
+            a, _, _, _ = mns.fit_phase2(I, mns.downsample(img), [x], [y], 8, 2, [int(m[idx])], t)
+            assert bool(a[0]) == stored, (x, y, t, mse)
 
 
 def test_no_search_variant_has_no_phase2_records():
