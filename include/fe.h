@@ -234,18 +234,43 @@ fe_status fe_encode(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t 
                     size_t* n_out, void* stream);
 
 /*
- * Encode a batch of images of any sides in one pass (one launch covers
- * every range of every image).  Image k's stream is written to
+ * Encode a batch of images of any sides in one pass (MNS, Sec. 3 and
+ * 3.1-3.3, for every image of the list; one launch covers every range of
+ * every image).  Image k's stream is written to
  * d_out[d_offsets[k] .. d_offsets[k+1]); d_offsets (device, n_imgs + 1
  * entries) is written by the device.  If n_out is not NULL the call waits
  * and stores the total count (FE_ERR_CAPACITY as for fe_encode); if it is
  * NULL the call returns at once and the caller must check
  * d_offsets[n_imgs] <= cap itself (entries beyond cap are not written).
- * FE_FULL_SEARCH is not accepted here.
+ * FE_FULL_SEARCH is not accepted here.  Trees down to 2 x 2 address record
+ * slots in 32 bits: a batch needing 2^32 slots or more gives FE_ERR_SHAPE.
  */
 fe_status fe_encode_batch(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
                           const fe_params* params, fe_transform* d_out, size_t cap,
                           uint64_t* d_offsets, size_t* n_out, void* stream);
+
+/*
+ * For callers that cannot allocate device memory during the call: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same MNS encode as fe_encode (same kernels, same stream),
+ * with every scratch buffer taken from a static device array of 32 MiB per
+ * GPU, held by the library until the process ends; the call makes no device
+ * or host allocation and copies nothing from the host (its image entry is
+ * written by a kernel).  The stream goes to d_out[0 .. d_offsets[1]);
+ * d_offsets (device, 2 entries, 8-byte aligned) receives 0 and the stream
+ * length.  If n_out is not NULL the call waits and stores the length
+ * (FE_ERR_CAPACITY as for fe_encode); if it is NULL it returns at once and
+ * the caller checks d_offsets[1] <= cap (entries beyond cap are not
+ * written).  An image whose scratch (about W*H bytes at b_min = 4, 5 W*H at
+ * b_min = 2, plus tile masks and descriptors) exceeds the 32 MiB gives
+ * FE_ERR_CAPACITY before any launch.  MNS and no-search only
+ * (FE_FULL_SEARCH / FE_LOCAL_SEARCH: FE_ERR_INVALID).  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (on different streams, threads or contexts) race.
+ */
+fe_status fe_encode_noalloc(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, uint32_t height,
+                            uint32_t stride, const fe_params* params, fe_transform* d_out, size_t cap,
+                            uint64_t* d_offsets, size_t* n_out, void* stream);
 
 /*
  * Recorded batch encode (a HIP graph).  fe_plan_create validates the batch

@@ -92,6 +92,8 @@ _SIGNATURES = {
     "fe_range_moments": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_encode": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params), _VP, _SZ,
                                  ctypes.POINTER(_SZ), _VP]),
+    "fe_encode_noalloc": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params), _VP, _SZ, _VP,
+                                         ctypes.POINTER(_SZ), _VP]),
     "fe_encode_batch": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params),
                                        _VP, _SZ, _VP, ctypes.POINTER(_SZ), _VP]),
     "fe_plan_create": (ctypes.c_int, [_VP, ctypes.POINTER(fe_image_desc), _U32, ctypes.POINTER(fe_params), _VP, _SZ,
@@ -245,6 +247,18 @@ def fe_encode(ctx: int, img, params: fe_params, out=None, stream=None):
     _check(load().fe_encode(ctx, _ptr(img), W, H, img.stride(0), ctypes.byref(params), _ptr(out),
                             out.shape[0], ctypes.byref(n), _stream(stream)))
     return out[: n.value]
+
+
+def fe_encode_noalloc(ctx: int, img, params: fe_params, out, offsets, wait: bool = True, stream=None):
+    """The allocation-free encode: `out` ((cap, 16) uint8) and `offsets`
+    (2 int64) are caller-owned device tensors.  Returns (out[:n], n) with
+    wait=True, (out, None) with wait=False (the length is offsets[1])."""
+    H, W = img.shape
+    n = _SZ(0)
+    _check(load().fe_encode_noalloc(ctx, _ptr(img), W, H, img.stride(0), ctypes.byref(params), _ptr(out),
+                                    out.shape[0], _ptr(offsets), ctypes.byref(n) if wait else None,
+                                    _stream(stream)))
+    return (out[: n.value], n.value) if wait else (out, None)
 
 
 def fe_encode_batch(ctx: int, imgs, params: fe_params, out=None, offsets=None, wait: bool = True,

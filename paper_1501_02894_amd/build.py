@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["mns_encode.hip", "mns_fine.hip", "order.hip", "mns_steps.hip", "decode.hip", "fullsearch.hip", "bitstream.hip",
+HIP_SOURCES = ["mns_encode.hip", "mns_fine.hip", "order.hip", "mns_steps.hip", "decode.hip", "fullsearch.hip", "bitstream.hip", "noalloc.hip",
                "bitstream_host.cpp", "server.cpp",
                "fe_host.cpp", "fe_common.cpp"]
 

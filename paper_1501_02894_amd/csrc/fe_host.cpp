@@ -8,6 +8,7 @@
 
 #include "fe.h"
 #include "fe_common.h"
+#include "fe_encode_seq.h"
 #include "fe_internal.h"
 
 struct fe_ctx {
@@ -160,7 +161,7 @@ struct Timed {
   hipStream_t s;
   int idx = -1;
   Timed(fe_ctx* ctx, int slot, hipStream_t stream) : c(ctx), s(stream) {
-    if (!c->timing || !c->ev || c->ev_used >= fe_ctx::kTimingCap || !((c->timing_mask >> slot) & 1u)) return;
+    if (!c || !c->timing || !c->ev || c->ev_used >= fe_ctx::kTimingCap || !((c->timing_mask >> slot) & 1u)) return;
     idx = c->ev_used++;
     c->ev_slot[idx] = slot;
     (void)hipEventRecord(c->ev[2 * idx], s);
@@ -260,12 +261,12 @@ fe_status check_batch(const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_par
 // Image table of a batch for `shape`: per image its tiles, workgroup blocks,
 // first workgroup and first tile.  Returns the totals.
 fe_status build_table(const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p, fe::TileShape shape,
-                      std::vector<fe::ImgDev>& table, uint64_t& tiles, uint32_t& wgs) {
-  table.assign(n_imgs, fe::ImgDev{});
+                      fe::ImgDev* table, uint64_t& tiles, uint32_t& wgs) {
   tiles = 0;
   wgs = 0;
   for (uint32_t k = 0; k < n_imgs; ++k) {
     fe::ImgDev& d = table[k];
+    d = fe::ImgDev{};
     d.data = imgs[k].data;
     d.width = imgs[k].width;
     d.height = imgs[k].height;
@@ -310,113 +311,144 @@ fe::TileShape choose_shape(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_im
   return shape;
 }
 
+}  // namespace
+
+namespace fe {
+
+fe_status encode_geometry(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
+                          ImgDev* table, EncodeGeom& g) {
+  // b_min = 2: the fused kernel runs the tree down to 4 x 4 (its EXT form)
+  // and the 2 x 2 level follows in a kernel of its own
+  g.ext = p->b_min < 4;
+  g.L = levels_of(p->b_max, g.ext ? 4u : p->b_min);   // fused levels
+  g.bmax = (int)p->b_max;
+  g.shape = choose_shape(ctx, imgs, n_imgs, p, g.L, g.ext);
+  if (g.shape.gx <= 0) return fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", g.bmax, g.L);
+  g.cells = 1 << (2 * (g.L - 1 + (g.ext ? 1 : 0)));
+  fe_status st = build_table(imgs, n_imgs, p, g.shape, table, g.tiles, g.wgs);
+  if (st != FE_OK) return st;
+  g.chunks = (size_t)((g.tiles + kChunkTiles - 1) / kChunkTiles);
+  g.slots = (uint64_t)g.wgs * (uint64_t)(g.shape.gx * g.shape.gy) * (uint64_t)g.cells;
+  g.fine_max = g.ext ? g.tiles * (uint64_t)(g.bmax / 4) * (uint64_t)(g.bmax / 4) : 0;
+  // the 2 x 2 level's list names each child's record slot in 32 bits
+  if (g.ext && g.slots >= (1ull << 32))
+    return fail(FE_ERR_SHAPE, "batch too large for 2 x 2 ranges (%llu record slots, at most 2^32)",
+                (unsigned long long)g.slots);
+  return FE_OK;
+}
+
+fe_status encode_launch(fe_ctx* ctx, const EncodeGeom& g, const EncodeBufs& b, uint32_t n_imgs, const fe_params* p,
+                        bool prep, fe_transform* d_out, size_t cap, uint64_t* offsets, hipStream_t s) {
+  if (prep) FE_HIP(launch_block_prep(b.table, n_imgs, g.wgs, g.bmax, g.shape.gx, g.shape.gy, b.blocks, s), "prep launch");
+  EncodeArgs a{};
+  a.imgs = b.table;
+  a.wg_first = table_wg_first(b.table, n_imgs);
+  a.blocks = b.blocks;
+  a.n_imgs = n_imgs;
+  a.n_wg = g.wgs;
+  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
+  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
+  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
+  a.staging = b.staging;
+  a.masks = b.masks;
+  if (g.ext) {
+    a.fine_list = b.fine_list;
+    a.fine_count = b.fine_count;
+    FE_HIP(launch_zero_u32(b.fine_count, 1, s), "zero 4 x 4 count");   // a kernel, not a memset
+  }
+  {
+    Timed t(ctx, FE_TIMING_ENCODE, s);
+    if (!g.ext) {
+      FE_HIP(launch_mns_tiles(g.bmax, g.L, g.shape, a, s), "encode kernel launch");
+    } else {
+      FE_HIP(launch_mns_tiles_ext(g.bmax, g.L, g.shape, a, s), "encode kernel launch");
+      FinishArgs f{};
+      f.imgs = b.table;
+      f.n_imgs = n_imgs;
+      f.list = b.fine_list;
+      f.count = b.fine_count;
+      f.gx = (uint32_t)g.shape.gx;
+      f.level = (uint32_t)g.L;
+      f.thr = p->mse_thr[g.L - 1];
+      f.phase2 = a.phase2;
+      f.identity_only = a.identity_only;
+      f.staging = b.staging;
+      f.masks = b.masks;
+      FE_HIP(launch_fine_finish(f, g.fine_max, s), "2 x 2 level launch");
+    }
+  }
+  {
+    Timed t(ctx, FE_TIMING_SCATTER, s);
+    FE_HIP(launch_scatter(b.table, n_imgs, n_imgs > 1 ? table_chunk_img(b.table, n_imgs) : nullptr, g.tiles, g.cells,
+                          g.shape, b.masks, b.chunk_sum, b.chunk_base, b.staging, reinterpret_cast<uint4*>(d_out),
+                          (uint64_t)cap, offsets, s),
+           "scatter kernel launch");
+  }
+  return FE_OK;
+}
+
+fe_status read_count(fe_ctx* ctx, const uint64_t* offsets, uint32_t n_imgs, size_t cap, size_t* n_out,
+                     hipStream_t s) {
+  FE_HIP(hipMemcpyAsync(ctx->h_scalars, offsets + n_imgs, sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+         "count read-back");
+  FE_HIP(hipStreamSynchronize(s), "encode");
+  *n_out = (size_t)ctx->h_scalars[0];
+  if (*n_out > cap) return fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
+  return FE_OK;
+}
+
+int ctx_device(const fe_ctx* ctx) { return ctx->device; }
+
+}  // namespace fe
+
+namespace {
+
 // Shared MNS encode of a list of images with common parameters.
 fe_status encode_images(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_imgs, const fe_params* p,
                         fe_transform* d_out, size_t cap, uint64_t* d_offsets, size_t* n_out, hipStream_t s) {
-  // b_min = 2: the fused kernel runs the tree down to 4 x 4 (its EXT form)
-  // and the 2 x 2 level follows in a kernel of its own
-  const bool ext = p->b_min < 4;
-  const int L = fe::levels_of(p->b_max, ext ? 4u : p->b_min);   // fused levels
-  const int bmax = (int)p->b_max;
-  const fe::TileShape shape = choose_shape(ctx, imgs, n_imgs, p, L, ext);
-  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
-  const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));
-  std::vector<fe::ImgDev> table;
-  uint64_t tiles = 0;
-  uint32_t wgs = 0;
-  fe_status st = build_table(imgs, n_imgs, p, shape, table, tiles, wgs);
+  std::vector<fe::ImgDev> table(n_imgs);
+  fe::EncodeGeom g;
+  fe_status st = fe::encode_geometry(ctx, imgs, n_imgs, p, table.data(), g);
   if (st != FE_OK) return st;
-  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
   // record slots: one group of NT * cells per workgroup block
-  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)wgs * (size_t)(shape.gx * shape.gy) * cells,
-                  "record staging")) != FE_OK)
-    return st;
-  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
-  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;
-  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, chunks + 1, "chunk bases")) != FE_OK) return st;
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)g.slots, "record staging")) != FE_OK) return st;
+  if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)g.tiles, "tile masks")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, g.chunks, "chunk sums")) != FE_OK) return st;
+  if ((st = ensure(ctx->chunk_base, ctx->chunk_base_n, g.chunks + 1, "chunk bases")) != FE_OK) return st;
   const size_t blocks_cap = ctx->blocks_n;
-  if ((st = ensure(ctx->blocks, ctx->blocks_n, (size_t)wgs, "block descriptors")) != FE_OK) return st;
+  if ((st = ensure(ctx->blocks, ctx->blocks_n, (size_t)g.wgs, "block descriptors")) != FE_OK) return st;
   if (ctx->blocks_n != blocks_cap) ctx->blocks_valid = false;   // reallocated
   uint64_t* offsets = d_offsets;
   if (!offsets) {
     if ((st = ensure(ctx->offsets, ctx->offsets_n, (size_t)n_imgs + 1, "offsets")) != FE_OK) return st;
     offsets = ctx->offsets;
   }
-  const uint64_t fine_max = ext ? tiles * (uint64_t)(bmax / 4) * (uint64_t)(bmax / 4) : 0;
-  if (ext) {
-    if ((st = ensure(ctx->fine_list, ctx->fine_list_n, (size_t)fine_max, "4 x 4 range list")) != FE_OK) return st;
+  if (g.ext) {
+    if ((st = ensure(ctx->fine_list, ctx->fine_list_n, (size_t)g.fine_max, "4 x 4 range list")) != FE_OK) return st;
     if ((st = ensure(ctx->fine_count, ctx->fine_count_n, 1, "4 x 4 range count")) != FE_OK) return st;
   }
-  if ((st = upload_table(ctx, table.data(), n_imgs, tiles, s)) != FE_OK) return st;
+  if ((st = upload_table(ctx, table.data(), n_imgs, g.tiles, s)) != FE_OK) return st;
 
   // block descriptors: rebuilt unless they were built from this very table
   // and shape (the buffer is only written here)
-  if (!ctx->blocks_valid || ctx->blocks_gen != ctx->table_gen || ctx->blocks_key[0] != bmax ||
-      ctx->blocks_key[1] != shape.gx || ctx->blocks_key[2] != shape.gy) {
+  if (!ctx->blocks_valid || ctx->blocks_gen != ctx->table_gen || ctx->blocks_key[0] != g.bmax ||
+      ctx->blocks_key[1] != g.shape.gx || ctx->blocks_key[2] != g.shape.gy) {
     ctx->blocks_valid = false;
-    FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, ctx->blocks, s),
+    FE_HIP(fe::launch_block_prep(ctx->d_table, n_imgs, g.wgs, g.bmax, g.shape.gx, g.shape.gy, ctx->blocks, s),
            "prep launch");
     FE_HIP(hipEventRecord(ctx->blocks_ready, s), "blocks event");
     ctx->blocks_valid = true;
     ctx->blocks_gen = ctx->table_gen;
-    ctx->blocks_key[0] = bmax;
-    ctx->blocks_key[1] = shape.gx;
-    ctx->blocks_key[2] = shape.gy;
+    ctx->blocks_key[0] = g.bmax;
+    ctx->blocks_key[1] = g.shape.gx;
+    ctx->blocks_key[2] = g.shape.gy;
   } else {
     FE_HIP(hipStreamWaitEvent(s, ctx->blocks_ready, 0), "wait for block descriptors");
   }
-  fe::EncodeArgs a{};
-  a.imgs = ctx->d_table;
-  a.wg_first = table_wg_first(ctx->d_table, n_imgs);
-  a.blocks = ctx->blocks;
-  a.n_imgs = n_imgs;
-  a.n_wg = wgs;
-  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
-  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
-  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
-  a.staging = ctx->staging;
-  a.masks = ctx->masks;
-  if (ext) {
-    a.fine_list = ctx->fine_list;
-    a.fine_count = ctx->fine_count;
-    FE_HIP(fe::launch_zero_u32(ctx->fine_count, 1, s), "zero 4 x 4 count");
-  }
-  {
-    Timed t(ctx, FE_TIMING_ENCODE, s);
-    if (!ext) {
-      FE_HIP(fe::launch_mns_tiles(bmax, L, shape, a, s), "encode kernel launch");
-    } else {
-      FE_HIP(fe::launch_mns_tiles_ext(bmax, L, shape, a, s), "encode kernel launch");
-      fe::FinishArgs f{};
-      f.imgs = ctx->d_table;
-      f.n_imgs = n_imgs;
-      f.list = ctx->fine_list;
-      f.count = ctx->fine_count;
-      f.gx = (uint32_t)shape.gx;
-      f.level = (uint32_t)L;
-      f.thr = p->mse_thr[L - 1];
-      f.phase2 = a.phase2;
-      f.identity_only = a.identity_only;
-      f.staging = ctx->staging;
-      f.masks = ctx->masks;
-      FE_HIP(fe::launch_fine_finish(f, fine_max, s), "2 x 2 level launch");
-    }
-  }
-  {
-    Timed t(ctx, FE_TIMING_SCATTER, s);
-    FE_HIP(fe::launch_scatter(ctx->d_table, n_imgs, table_chunk_img(ctx->d_table, n_imgs), tiles, cells, shape,
-                              ctx->masks, ctx->chunk_sum, ctx->chunk_base,
-                              ctx->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, offsets, s),
-           "scatter kernel launch");
-  }
-  if (n_out) {
-    FE_HIP(hipMemcpyAsync(ctx->h_scalars, offsets + n_imgs, sizeof(uint64_t), hipMemcpyDeviceToHost, s),
-           "count read-back");
-    FE_HIP(hipStreamSynchronize(s), "encode");
-    *n_out = (size_t)ctx->h_scalars[0];
-    if (*n_out > cap)
-      return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, *n_out);
-  }
+  const fe::EncodeBufs b{ctx->d_table, ctx->blocks, ctx->staging, ctx->masks, ctx->chunk_sum, ctx->chunk_base,
+                         ctx->fine_list, ctx->fine_count};
+  if ((st = fe::encode_launch(ctx, g, b, n_imgs, p, false, d_out, cap, offsets, s)) != FE_OK) return st;
+  if (n_out) return fe::read_count(ctx, offsets, n_imgs, cap, n_out, s);
   return FE_OK;
 }
 
@@ -545,6 +577,11 @@ fe_status fe_create(int device, fe_ctx** out) {
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     fe_destroy(c);
     return fe::fail(FE_ERR_OOM, "context allocation failed");
+  }
+  // the allocation-free encode's scratch: its address on this device
+  if (fe_status st = fe::static_scratch_init(device); st != FE_OK) {
+    fe_destroy(c);
+    return st;
   }
   *out = c;
   return FE_OK;
@@ -1038,18 +1075,12 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   fe_status st = check_batch(h_imgs, n_imgs, p, d_out, d_offsets);
   if (st != FE_OK) return st;
   DeviceGuard g(ctx->device);
-  const bool ext = p->b_min < 4;   // down to 2 x 2: EXT form, then the 2 x 2 level
-  const int L = fe::levels_of(p->b_max, ext ? 4u : p->b_min);
-  const int bmax = (int)p->b_max;
-  const fe::TileShape shape = choose_shape(ctx, h_imgs, n_imgs, p, L, ext);
-  if (shape.gx <= 0) return fe::fail(FE_ERR_INVALID, "no kernel for b_max=%d with %d levels", bmax, L);
-  std::vector<fe::ImgDev> table;
-  uint64_t tiles = 0;
-  uint32_t wgs = 0;
-  if ((st = build_table(h_imgs, n_imgs, p, shape, table, tiles, wgs)) != FE_OK) return st;
-  const int cells = 1 << (2 * (L - 1 + (ext ? 1 : 0)));
-  const uint64_t fine_max = ext ? tiles * (uint64_t)(bmax / 4) * (uint64_t)(bmax / 4) : 0;
-  const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
+  std::vector<fe::ImgDev> table(n_imgs);
+  fe::EncodeGeom geo;
+  if ((st = fe::encode_geometry(ctx, h_imgs, n_imgs, p, table.data(), geo)) != FE_OK) return st;
+  const bool ext = geo.ext;
+  const uint64_t tiles = geo.tiles;
+  const uint32_t wgs = geo.wgs;
   fe_plan* pl = new fe_plan();
   pl->device = ctx->device;
   pl->n_imgs = n_imgs;
@@ -1059,12 +1090,11 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_table), slots * sizeof(fe::ImgDev));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->blocks), std::max<size_t>(wgs, 1) * sizeof(fe::BlockDesc));
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void**>(&pl->staging),
-                  std::max<size_t>((size_t)wgs * (size_t)(shape.gx * shape.gy) * cells, 1) * 16);
+    e = hipMalloc(reinterpret_cast<void**>(&pl->staging), std::max<size_t>((size_t)geo.slots, 1) * 16);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->masks), std::max<size_t>(tiles, 1) * 8);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_sum), std::max<size_t>(chunks, 1) * 4);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_base), (chunks + 1) * 8);
-  if (e == hipSuccess && ext) e = hipMalloc(reinterpret_cast<void**>(&pl->fine_list), std::max<uint64_t>(fine_max, 1) * 16);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_sum), std::max<size_t>(geo.chunks, 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->chunk_base), (geo.chunks + 1) * 8);
+  if (e == hipSuccess && ext) e = hipMalloc(reinterpret_cast<void**>(&pl->fine_list), std::max<uint64_t>(geo.fine_max, 1) * 16);
   if (e == hipSuccess && ext) e = hipMalloc(reinterpret_cast<void**>(&pl->fine_count), 4);
   if (e == hipSuccess) e = hipMemcpy(pl->d_table, host.data(), slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
@@ -1074,49 +1104,16 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     return hip_fail(e, "plan allocation");
   }
   pl->ctx = ctx;
-  // record the launch sequence once; replays re-read the images in place
-  fe::EncodeArgs a{};
-  a.imgs = pl->d_table;
-  a.wg_first = table_wg_first(pl->d_table, n_imgs);
-  a.blocks = pl->blocks;
-  a.n_imgs = n_imgs;
-  a.n_wg = wgs;
-  a.phase2 = (p->flags & FE_PHASE2) ? 1u : 0u;
-  a.identity_only = (p->flags & FE_IDENTITY_ONLY) ? 1u : 0u;
-  for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
-  a.staging = pl->staging;
-  a.masks = pl->masks;
-  a.fine_list = pl->fine_list;
-  a.fine_count = pl->fine_count;
+  // record the launch sequence once; replays re-read the images in place.
+  // Chain: prep, [zero count], encode, [2 x 2 level], ordering; the count
+  // is cleared by a kernel, not a memset node.
   e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    // chain: prep, [zero count], encode, [2 x 2 level], ordering; the count
-    // is cleared by a kernel, not a memset node
-    hipError_t le = fe::launch_block_prep(pl->d_table, n_imgs, wgs, bmax, shape.gx, shape.gy, pl->blocks, pl->capture);
-    if (le == hipSuccess && ext) le = fe::launch_zero_u32(pl->fine_count, 1, pl->capture);
-    if (le == hipSuccess)
-      le = ext ? fe::launch_mns_tiles_ext(bmax, L, shape, a, pl->capture) : fe::launch_mns_tiles(bmax, L, shape, a, pl->capture);
-    if (le == hipSuccess && ext) {
-      fe::FinishArgs f{};
-      f.imgs = pl->d_table;
-      f.n_imgs = n_imgs;
-      f.list = pl->fine_list;
-      f.count = pl->fine_count;
-      f.gx = (uint32_t)shape.gx;
-      f.level = (uint32_t)L;
-      f.thr = p->mse_thr[L - 1];
-      f.phase2 = a.phase2;
-      f.identity_only = a.identity_only;
-      f.staging = pl->staging;
-      f.masks = pl->masks;
-      le = fe::launch_fine_finish(f, fine_max, pl->capture);
-    }
-    if (le == hipSuccess)
-      le = fe::launch_scatter(pl->d_table, n_imgs, table_chunk_img(pl->d_table, n_imgs), tiles, cells, shape,
-                              pl->masks, pl->chunk_sum, pl->chunk_base,
-                              pl->staging, reinterpret_cast<uint4*>(d_out), (uint64_t)cap, d_offsets, pl->capture);
+    const fe::EncodeBufs b{pl->d_table, pl->blocks, pl->staging, pl->masks, pl->chunk_sum, pl->chunk_base,
+                           pl->fine_list, pl->fine_count};
+    const fe_status ls = fe::encode_launch(nullptr, geo, b, n_imgs, p, true, d_out, cap, d_offsets, pl->capture);
     e = hipStreamEndCapture(pl->capture, &pl->graph);
-    if (le != hipSuccess) e = le;
+    if (ls != FE_OK && e == hipSuccess) e = hipErrorLaunchFailure;
   }
   if (e != hipSuccess) {
     fe_plan_destroy(pl);
