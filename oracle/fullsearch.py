@@ -63,13 +63,18 @@ def best_matches(img: np.ndarray, xs, ys, B: int, chunk: int | None = None):
     sdd = (D * D).sum(axis=1)
     Q = n * sdd - sd * sd
     Df = D.astype(np.float64)
+    # T_e(d)[p] = d[src_e(p)] with src_e a permutation of the n positions, so
+    # Sum_p r[p] T_e(d)[p] = Sum_q r_e[q] d[q] where r_e[src_e(p)] = r[p]: the
+    # range is moved to the domain positions the isometry reads, and one
+    # matrix product gives every (domain, isometry) pair at once
     flat_src = []
     for e in range(8):
         rows, cols = isometry_source(e, B)
         flat_src.append((rows * B + cols).ravel())
     R = xs.size
+    ND = D.shape[0]
     if chunk is None:
-        chunk = max(1, (1 << 24) // (8 * D.shape[0]))
+        chunk = max(1, (1 << 24) // (8 * ND))
     out = {k: np.zeros(R, np.int64) for k in ("dom", "u", "v", "e", "k", "m", "S")}
     ii = np.arange(B)
     for s in range(0, R, chunk):
@@ -79,12 +84,15 @@ def best_matches(img: np.ndarray, xs, ys, B: int, chunk: int | None = None):
         sr = r.sum(axis=1)
         srr = (r * r).sum(axis=1)
         c = r.shape[0]
-        f = np.empty((c, D.shape[0], 8), np.int64)
-        kk = np.empty((c, D.shape[0], 8), np.int64)
+        re = np.empty((8, c, n), np.float64)
         for e in range(8):
-            # Sum_p r[p] * T_e(d)[p] for every domain (rows of D) and range
-            srd = np.rint(Df[:, flat_src[e]] @ r.T.astype(np.float64)).astype(np.int64)  # (ND, c)
-            P = n * srd.T - sr[:, None] * sd[None, :]
+            re[e][:, flat_src[e]] = r
+        # (ND, 8 c): Sum r T_e(d) for every domain, isometry and range
+        srd_all = np.rint(Df @ re.reshape(8 * c, n).T).astype(np.int64).reshape(ND, 8, c)
+        f = np.empty((c, ND, 8), np.int64)
+        kk = np.empty((c, ND, 8), np.int64)
+        for e in range(8):
+            P = n * srd_all[:, e, :].T - sr[:, None] * sd[None, :]
             k = closed_form_k(P, Q[None, :])
             kk[:, :, e] = k
             f[:, :, e] = k * k * Q[None, :] - 16 * k * P

@@ -8,6 +8,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle_pool
 from oracle import decode as odec
 from oracle import fullsearch, mns
 from paper_1501_02894_amd import binding as fb
@@ -15,7 +16,8 @@ from paper_1501_02894_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-SAMPLES = int(os.environ.get("FE_FS_SAMPLES", "24"))
+# ranges of the C2 exhaustive search checked against the oracle
+C2_SAMPLES = int(os.environ.get("FE_FS_SAMPLES", "4096"))
 
 
 def log(msg):
@@ -95,40 +97,65 @@ def test_full_search_encode_small(torch_dev, ctx, H, W, bmax, bmin, thr):
     assert got.tobytes() == np.ascontiguousarray(want).tobytes()
 
 
+def evaluated_ranges(rec, b_max: int, levels: int):
+    """Per level, the ranges the quadtree evaluated: every record's ancestor
+    (or itself) at that level, i.e. the level's accepted ranges and the ones
+    it split.  Returns a list of (xs, ys) arrays."""
+    out = []
+    x, y, lv = (rec[k].astype(np.int64) for k in ("x", "y", "level"))
+    for level in range(levels):
+        B = b_max >> level
+        sel = lv >= level
+        key = np.unique(((y[sel] // B) << 20) | (x[sel] // B))
+        out.append(((key & 0xfffff) * B, (key >> 20) * B))
+    return out
+
+
 @pytest.mark.slow
 def test_full_search_c2_sampled(torch_dev, ctx):
-    """C2 (512^2, 16->8->4): sampled ranges of every level, checked one by
-    one against the oracle's exhaustive definition; the stream's structure
-    and decisions checked at every record."""
+    """C2 (512^2, 16->8->4): up to 4096 ranges drawn uniformly (seed 2) from
+    the ranges the exhaustive quadtree evaluated at its three levels (it
+    evaluates fewer than that on C2, about 1500, so all of them), each checked
+    against the oracle's exhaustive definition (best domain, isometry,
+    contrast, luminance and error); a sampled range is a record of the stream
+    exactly when the oracle's error is below the level's threshold (or the
+    level is the last), with the oracle's fields.  The stream's structure is
+    checked at every record."""
     log("full-search encode c2")
     img = synth.workload("c2")
     thr = [300, 200]
     got = fb.to_records(ctx.encode(dev(torch_dev, img), 16, 4, thr, full_search=True))
     odec.decode(got, 512, 512, 16, 1)           # tiles the image exactly once
+    ev = evaluated_ranges(got, 16, 3)
+    sizes = [xs.size for xs, _ in ev]
+    total = sum(sizes)
     rng = np.random.default_rng(2)
-    for level in range(3):
-        B = 16 >> level
-        sel = np.flatnonzero(got["level"] == level)
-        if sel.size == 0:
-            continue
-        pick = rng.choice(sel, min(SAMPLES, sel.size), replace=False)
-        log(f"  level {level + 1}: checking {pick.size} of {sel.size} records")
-        want = fullsearch.best_matches(img, got["x"][pick], got["y"][pick], B)
-        nu = 512 - 2 * B + 1
-        dom = got["dy"][pick].astype(np.int64) * nu + got["dx"][pick]
-        np.testing.assert_array_equal(dom, want["dom"])
-        np.testing.assert_array_equal(got["iso"][pick], want["e"])
-        np.testing.assert_array_equal(got["s_idx"][pick], want["k"])
-        np.testing.assert_array_equal(got["lum"][pick], want["m"])
-        if level < 2:   # accepted before the forced last level
-            assert np.all(want["S"] < 64 * (B * B) ** 2 * thr[level])
-    # arbitrary ranges (including ones the quadtree split) at every size
-    for B in (16, 8, 4):
-        n = 512 // B
-        idx = rng.choice(n * n, SAMPLES, replace=False)
-        xs, ys = (idx % n) * B, (idx // n) * B
-        assert_best_equal(gpu_best(torch_dev, ctx, img, B, xs, ys), fullsearch.best_matches(img, xs, ys, B),
-                          f"c2 B={B}")
+    pick = np.sort(rng.choice(total, min(C2_SAMPLES, total), replace=False))
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    with oracle_pool.pool() as ex:
+        jobs = []
+        for level in range(3):
+            B = 16 >> level
+            sel = pick[(pick >= bounds[level]) & (pick < bounds[level + 1])] - bounds[level]
+            xs, ys = ev[level][0][sel], ev[level][1][sel]
+            log(f"  level {level + 1}: checking {sel.size} of {sizes[level]} evaluated ranges")
+            jobs.append((level, B, xs, ys, oracle_pool.best_matches(ex, img, xs, ys, B)))
+        rec_at = {(int(x), int(y), int(l)): i for i, (x, y, l) in
+                  enumerate(zip(got["x"], got["y"], got["level"]))}
+        for level, B, xs, ys, futs in jobs:
+            parts = [f.result() for f in futs]
+            want = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+            assert_best_equal(gpu_best(torch_dev, ctx, img, B, xs, ys), want, f"c2 level {level + 1}")
+            n = B * B
+            accept = np.ones(xs.size, bool) if level == 2 else want["S"] < 64 * n * n * thr[level]
+            for j in range(xs.size):
+                i = rec_at.get((int(xs[j]), int(ys[j]), level))
+                assert (i is not None) == bool(accept[j]), f"level {level + 1} range ({xs[j]}, {ys[j]})"
+                if i is not None:
+                    assert (int(got["dx"][i]), int(got["dy"][i])) == (int(want["u"][j]), int(want["v"][j]))
+                    assert (int(got["iso"][i]), int(got["s_idx"][i]), int(got["lum"][i])) == \
+                        (int(want["e"][j]), int(want["k"][j]), int(want["m"][j]))
+            log(f"  level {level + 1}: {xs.size} ranges equal the oracle ({int(accept.sum())} stored)")
 
 
 def test_full_search_not_worse_than_mns(torch_dev, ctx):

@@ -364,3 +364,34 @@ def test_decode_zero_iterations_and_bad_input(torch_dev, ctx):
     assert ei.value.status == fb.FE_ERR_INVALID
 
 
+
+
+def test_autotune_picks_a_built_shape(torch_dev, ctx):
+    """The autotuner times every built tile shape on the caller's batch and
+    selects the fastest for the context; the streams it then produces equal
+    the oracle's (the shape never changes the output)."""
+    torch = torch_dev
+    rng = np.random.default_rng(11)
+    imgs = []
+    for k in range(6):
+        H, W = (int(v) for v in rng.choice([128, 160, 256, 352], 2))
+        imgs.append(synth.noise_1f(H, W, 300 + k) if k % 2 else synth.piecewise_smooth(H, W, 300 + k, cells=12))
+    views = [dev(torch, im) for im in imgs]
+    thr = [300, 200]
+    params = fb.make_params(16, 4, thr)
+    cap = sum(fb.fe_max_transforms(im.shape[1], im.shape[0], 4) for im in imgs)
+    out = torch.empty((cap, 16), dtype=torch.uint8, device="cuda")
+    offsets = torch.zeros(len(imgs) + 1, dtype=torch.int64, device="cuda")
+    try:
+        (gx, gy), ms = fb.fe_autotune(ctx.handle, views, params, out, offsets, reps=2)
+        log(f"  autotune: {gx}x{gy}, {ms * 1e3:.1f} us")
+        assert (gx, gy) in fb.fe_tile_shapes(16, 4)
+        assert ms > 0
+        assert fb.fe_get_tile_shape(ctx.handle, 16, 4) == (gx, gy)
+        got, offs, n = ctx.encode_batch(views, 16, 4, thr)
+        o = offs.cpu().numpy()
+        recs = fb.to_records(got[:n])
+        for k, im in enumerate(imgs):
+            assert_same_stream(recs[o[k]:o[k + 1]], mns.encode(im, 16, 4, thr))
+    finally:
+        fb.fe_set_tile_shape(ctx.handle, 16, 4, 0, 0)
