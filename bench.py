@@ -436,6 +436,7 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     t0 = time.perf_counter() + 0.05
     if mode == "server":
         lat = np.zeros(total)
+        stages = np.zeros((total, 4))
         index = {}
 
         def submitter():
@@ -461,12 +462,14 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
             rid = srv.wait(2000)          # blocks in the library, GIL released
             if rid is None:
                 continue
+            st = srv.request_times(rid)
             ok, recs, l = srv.poll(rid)
             while rid not in index:      # the submitter has not recorded it yet
                 time.sleep(0)
             i = index[rid]
             finished += 1
             done_at[i] = time.perf_counter() - t0
+            stages[i] = st
             lat[i] += l / 1e3
         th.join()
         stats = srv.stats()
@@ -492,6 +495,14 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
            "mean_px": float(np.mean([pool[k].numel() for k in which[m]]))}
     if stats:
         res["steps"] = stats["steps"]
+        # where the server's latency goes: submit delay (arrival to submit
+        # returning), then admitted, first step, last step and complete,
+        # each in ms after submission (p50 / p99 over the measured requests)
+        sd = lat[m] * 1e3 - stages[m, 3]
+        res["stages_ms"] = {name: [float(np.percentile(v, 50)), float(np.percentile(v, 99))]
+                            for name, v in (("submit_delay", sd), ("admitted", stages[m, 0]),
+                                            ("first_step", stages[m, 1]), ("last_step", stages[m, 2]),
+                                            ("complete", stages[m, 3]))}
     return res
 
 
@@ -532,9 +543,13 @@ def main():
                                                              "single-image, decode and full-search runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for counter scaling)")
-    ap.add_argument("--serve-rates", default="500,2000,8000,20000,40000")
-    ap.add_argument("--serve-requests", type=int, default=600)
-    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000",
+                    help="Poisson arrival rates (requests/s) of the served-encoding sweep")
+    ap.add_argument("--serve-extra-rates", default="8000,20000",
+                    help="rates beyond the sweep, toward saturation")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-pool", type=int, default=512)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--decode-only", action="store_true",
                     help="only decode C3 (4096^2, 32 -> 4) with both decoders (a profiling workload)")
@@ -544,6 +559,7 @@ def main():
                     help="only the 16 -> 2 tree against 16 -> 4 on C2 and C3, and zoom decoding")
     ap.add_argument("--fullsearch-only", action="store_true",
                     help="only the exhaustive-search encode of C2 (512^2, 16 -> 4) (a profiling workload)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape (no autotuning)")
     ap.add_argument("--cpu-oracle-child", metavar="DIR", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_oracle_child:
@@ -561,6 +577,12 @@ def main():
         t_gen = time.perf_counter() - t_gen
         print(f"[bench] generated {len(images)} images in {t_gen:.1f}s", file=sys.stderr, flush=True)
         oracle_child = None if args.no_cpu_baseline else start_cpu_baseline(images)
+        serve_pool = None
+        if not args.no_serving:
+            t_gen = time.perf_counter()
+            serve_pool = pooled(_gen_c5, list(range(args.serve_pool)), 16)
+            print(f"[bench] generated the {len(serve_pool)}-image request pool in {time.perf_counter() - t_gen:.1f}s",
+                  file=sys.stderr, flush=True)
 
     import torch
     from paper_1501_02894_amd import binding as fb
@@ -625,9 +647,12 @@ def main():
     # events around the fused kernel) and selects the fastest for the
     # context; the timed steps and the recorded plan use it
     default_shape = fb.fe_get_tile_shape(ctx.handle, B_MAX, B_MIN)
-    tuned_shape, tuned_ms = fb.fe_autotune(ctx.handle, views, params, out, offsets, reps=5)
+    if args.no_autotune:
+        tuned_shape, tuned_ms = default_shape, None
+    else:
+        tuned_shape, tuned_ms = fb.fe_autotune(ctx.handle, views, params, out, offsets, reps=5)
     torch.cuda.synchronize()
-    print(f"[bench] autotuned tile shape {tuned_shape} ({tuned_ms * 1e3:.1f} us; default {default_shape})",
+    print(f"[bench] tile shape {tuned_shape} (autotune {tuned_ms}; default {default_shape})",
           file=sys.stderr, flush=True)
 
     def step():
@@ -865,13 +890,30 @@ def main():
             result["cpu_baseline"]["fullsearch"] = cpu_fullsearch_sample(synth.workload("c2"))
 
     if not args.no_serving:
-        pool = [torch.from_numpy(im).pin_memory() for im in pooled(_gen_c5, list(range(args.serve_pool)))]
-        serving = []
-        for rate in [float(r) for r in args.serve_rates.split(",")]:
-            for mode in ("server", "plain"):
-                serving.append(serve_run(fb, mode, pool, rate, args.serve_requests, 30, 5, ctx=ctx))
-                print(f"[bench] serving {mode} @ {rate}/s: {serving[-1]}", file=sys.stderr, flush=True)
+        pool = [torch.from_numpy(im).pin_memory() for im in serve_pool]
+        del serve_pool
+        def sweep(rates):
+            rows = []
+            for rate in [float(r) for r in rates.split(",") if r]:
+                for mode in ("server", "plain"):
+                    rows.append(serve_run(fb, mode, pool, rate, args.serve_requests, args.serve_warmup, 5, ctx=ctx))
+                    print(f"[bench] serving {mode} @ {rate}/s: {rows[-1]}", file=sys.stderr, flush=True)
+            return rows
+
+        serving = sweep(args.serve_rates)
+        extra = sweep(args.serve_extra_rates)
+        by = {(r["mode"], r["rate"]): r for r in serving + extra}
+        rates = sorted({r["rate"] for r in serving})
         result["serving"] = serving
+        result["serving_saturation"] = extra
+        result["serving_summary"] = {
+            "workload": f"c5: {len(pool)}-image pool, sides 64..4096 (x16), Poisson arrivals, "
+                        f"{args.serve_requests} requests after {args.serve_warmup} warm-up per rate",
+            "server_p99_le_plain_at_every_swept_rate": all(
+                by[("server", r)]["p99_ms"] <= by[("plain", r)]["p99_ms"] for r in rates),
+            "max_images_per_s": {m: max(v["images_per_s"] for k, v in by.items() if k[0] == m)
+                                 for m in ("server", "plain")},
+        }
 
     if args.copy_calibration:
         result["copy_calibration_bytes"] = copy_calibration(torch, dev)

@@ -493,6 +493,15 @@ fe_status fe_server_submit_pinned(fe_server* server, const uint8_t* h_img, uint3
 fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, size_t cap, size_t* n,
                          int* done, double* latency_ms);
 fe_status fe_server_wait(fe_server* server, uint32_t timeout_us, uint64_t* req);
+/*
+ * Where a request's latency went (execution; no passage of the paper): the
+ * times, in milliseconds after its submission, at which request `req` was
+ * admitted (its image copy issued), had its first and its last step
+ * launched, and was found complete, written to ms[0 .. min(n, 4)).  The
+ * request must be done and not yet fetched (FE_ERR_BUSY otherwise;
+ * FE_ERR_INVALID for an unknown id).
+ */
+fe_status fe_server_request_times(fe_server* server, uint64_t req, double* ms, uint32_t n);
 fe_status fe_server_stats(fe_server* server, uint64_t* steps, uint64_t* blocks, uint64_t* completed,
                           size_t* hbm_used, uint32_t* in_flight, uint32_t* queued);
 void fe_server_destroy(fe_server* server);

@@ -119,6 +119,7 @@ _SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_SZ), ctypes.POINTER(_U32),
                                        ctypes.POINTER(_U32)]),
     "fe_server_wait": (ctypes.c_int, [_VP, _U32, ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_request_times": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _U32]),
     "fe_server_destroy": (None, [_VP]),
     "fe_tile_shapes": (ctypes.c_int, [_U32, _U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.c_int]),
     "fe_set_tile_shape": (ctypes.c_int, [_VP, _U32, _U32, _U32, _U32]),
@@ -524,6 +525,14 @@ def fe_server_wait(server: int, timeout_us: int):
     return req.value
 
 
+def fe_server_request_times(server: int, req: int):
+    """(admitted, first step, last step, complete), ms after submission, of
+    a done request not yet fetched."""
+    ms = (ctypes.c_double * 4)()
+    _check(load().fe_server_request_times(server, req, ms, 4))
+    return tuple(ms)
+
+
 def fe_server_stats(server: int) -> dict:
     v = [ctypes.c_uint64(0) for _ in range(3)]
     used = _SZ(0)
@@ -557,6 +566,9 @@ class Server:
 
     def wait(self, timeout_us=1000):
         return fe_server_wait(self.handle, timeout_us)
+
+    def request_times(self, req):
+        return fe_server_request_times(self.handle, req)
 
     def stats(self):
         return fe_server_stats(self.handle)

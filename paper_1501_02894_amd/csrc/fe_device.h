@@ -46,19 +46,20 @@ __device__ __forceinline__ void team_reduce(uint32_t (&a)[N], int T) {
   }
 }
 
-// Q dwords of an LDS row starting at byte offset `off` of `arr`.
+// Q dwords of the LDS row starting at byte address p (4-byte aligned when
+// ALIGNED).
 template <int Q, bool ALIGNED>
-__device__ __forceinline__ void lds_row(const uint32_t* arr, int off, uint32_t (&o)[Q]) {
+__device__ __forceinline__ void lds_row_at(const uint8_t* p, uint32_t (&o)[Q]) {
   if constexpr (ALIGNED) {
-    const int w = off >> 2;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) o[q] = arr[w + q];
+    for (int q = 0; q < Q; ++q) o[q] = w[q];
   } else {
-    const int w = off >> 2;
-    const uint32_t sh = (uint32_t)off & 3u;
+    const uint32_t sh = (uint32_t)(uintptr_t)p & 3u;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p - sh);
     uint32_t v[Q + 1];
 #pragma unroll
-    for (int q = 0; q <= Q; ++q) v[q] = arr[w + q];
+    for (int q = 0; q <= Q; ++q) v[q] = w[q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) o[q] = __builtin_amdgcn_alignbyte(v[q + 1], v[q], sh);
   }
@@ -66,10 +67,10 @@ __device__ __forceinline__ void lds_row(const uint32_t* arr, int off, uint32_t (
 
 // Moment slots: 0 Sum r, 1 Sum r^2, 2 Sum d, 3 Sum d^2, 4+e Sum r T_e(d).
 //
-// Adds the contribution of range rows i and B-1-i.  The range is B x B at
-// byte offset r_off of `img` (row pitch rp, dword aligned); the domain d is
-// the B x B window at byte offset d_off of `h0` (pitch hp); its transpose
-// is at byte offset t_off of `h0t` (pitch tp), i.e. dT[i][j] = d[j][i].
+// Adds the contribution of range rows i and B-1-i, given by the LDS byte
+// addresses of their first pixels: range rows ra, rb (dword aligned), rows i
+// and B-1-i of the B x B domain window d (da, db) and of its transpose
+// (ta, tb), dT[i][j] = d[j][i].
 //
 // With rrev the range with each row reversed, the eight isometries of the
 // table T_e(d)[i][j] = d[i][j], d[i][B-1-j], d[B-1-i][j], d[B-1-i][B-1-j],
@@ -77,19 +78,17 @@ __device__ __forceinline__ void lds_row(const uint32_t* arr, int off, uint32_t (
 // (i' = B-1-i):  e0 r_i.d_i, e1 rrev_i.d_i, e2 r_i.d_i', e3 rrev_i.d_i',
 // e4 r_i.dT_i, e5 rrev_i.dT_i, e6 r_i.dT_i', e7 rrev_i.dT_i'.
 template <int B, bool ALIGNED>
-__device__ __forceinline__ void accumulate_row_pair(const uint32_t* img, int r_off, int rp,
-                                                    const uint32_t* h0, int d_off, int hp,
-                                                    const uint32_t* h0t, int t_off, int tp, int i,
-                                                    uint32_t (&a)[12]) {
+__device__ __forceinline__ void accumulate_rows(const uint8_t* rap, const uint8_t* rbp, const uint8_t* dap,
+                                                const uint8_t* dbp, const uint8_t* tap, const uint8_t* tbp,
+                                                uint32_t (&a)[12]) {
   constexpr int Q = B / 4;
-  const int ia = i, ib = B - 1 - i;
   uint32_t ra[Q], rb[Q], da[Q], db[Q], ta[Q], tb[Q];
-  lds_row<Q, true>(img, r_off + ia * rp, ra);
-  lds_row<Q, true>(img, r_off + ib * rp, rb);
-  lds_row<Q, ALIGNED>(h0, d_off + ia * hp, da);
-  lds_row<Q, ALIGNED>(h0, d_off + ib * hp, db);
-  lds_row<Q, ALIGNED>(h0t, t_off + ia * tp, ta);
-  lds_row<Q, ALIGNED>(h0t, t_off + ib * tp, tb);
+  lds_row_at<Q, true>(rap, ra);
+  lds_row_at<Q, true>(rbp, rb);
+  lds_row_at<Q, ALIGNED>(dap, da);
+  lds_row_at<Q, ALIGNED>(dbp, db);
+  lds_row_at<Q, ALIGNED>(tap, ta);
+  lds_row_at<Q, ALIGNED>(tbp, tb);
   const uint32_t ones = 0x01010101u;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -109,6 +108,22 @@ __device__ __forceinline__ void accumulate_row_pair(const uint32_t* img, int r_o
     a[10] = dot4(xa, tb[q], dot4(xb, ta[q], a[10]));
     a[11] = dot4(ya, tb[q], dot4(yb, ta[q], a[11]));
   }
+}
+
+// The same for the range at byte offset r_off of `img` (row pitch rp), the
+// domain window at byte offset d_off of `h0` (pitch hp) and its transpose at
+// byte offset t_off of `h0t` (pitch tp).
+template <int B, bool ALIGNED>
+__device__ __forceinline__ void accumulate_row_pair(const uint32_t* img, int r_off, int rp,
+                                                    const uint32_t* h0, int d_off, int hp,
+                                                    const uint32_t* h0t, int t_off, int tp, int i,
+                                                    uint32_t (&a)[12]) {
+  const int ia = i, ib = B - 1 - i;
+  const uint8_t* im = reinterpret_cast<const uint8_t*>(img);
+  const uint8_t* hd = reinterpret_cast<const uint8_t*>(h0);
+  const uint8_t* ht = reinterpret_cast<const uint8_t*>(h0t);
+  accumulate_rows<B, ALIGNED>(im + r_off + ia * rp, im + r_off + ib * rp, hd + d_off + ia * hp, hd + d_off + ib * hp,
+                              ht + t_off + ia * tp, ht + t_off + ib * tp, a);
 }
 
 // Phase-1 fit packed as: bits 0-7 m, 8-10 k, 11-13 e, bit 14 accept.
@@ -157,6 +172,49 @@ __device__ __forceinline__ uint32_t fit_phase1(const uint32_t (&m)[12], bool for
   const double S = f + 64.0 * R + 64.0 * (dm * dm);
   const bool acc = forced || S < (64.0 * N * N) * (double)t;
   return lum | ((uint32_t)k << 8) | ((uint32_t)e << 11) | (acc ? kFitAccept : 0u);
+}
+
+// The same phase-1 fit for the fused encoder, which also hands the terms
+// Technique 1 reuses to its caller.  The best isometry is found with one
+// key per isometry, Sum r T_e(d) << 3 | (7 - e) (every sum is below 2^27,
+// B <= 32), whose maximum is the largest sum at the lowest e.  `thr64` is
+// 64 n^2 t as a double, or +infinity at a forced level; every other
+// quantity is the exact integer arithmetic of fit_phase1.
+struct Fit1 {
+  double Q, R, srsd;   // n Sum d^2 - (Sum d)^2, n Sum r^2 - (Sum r)^2, Sum r Sum d
+  uint32_t lum, k, e;
+  bool accept;
+};
+
+template <int B>
+__device__ __forceinline__ Fit1 fit_phase1_terms(const uint32_t (&m)[12], double thr64) {
+  constexpr int LOGN = 2 * Log2<B>::value;
+  constexpr double N = (double)(B * B);
+  uint32_t key[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) key[j] = (m[4 + j] << 3) | (uint32_t)(7 - j);
+  const uint32_t k012 = max(max(key[0], key[1]), key[2]);
+  const uint32_t k345 = max(max(key[3], key[4]), key[5]);
+  const uint32_t top = max(max(k012, k345), max(key[6], key[7]));
+  Fit1 r;
+  const double sr = (double)m[0], sd = (double)m[2];
+  r.srsd = sr * sd;
+  r.Q = N * (double)m[3] - sd * sd;
+  r.R = N * (double)m[1] - sr * sr;
+  const double P = N * (double)(top >> 3) - r.srsd;
+  const double P16 = 16.0 * P;
+  // k = #{j in 0..6 : (2j+1) Q < 16 P}, a monotone predicate: three tests
+  uint32_t k = (7.0 * r.Q < P16) ? 4u : 0u;
+  k += ((double)(2 * k + 3) * r.Q < P16) ? 2u : 0u;
+  k += ((double)(2 * k + 1) * r.Q < P16) ? 1u : 0u;
+  r.k = k;
+  r.e = k ? 7u - (top & 7u) : 0u;
+  const double f = (double)(k * k) * r.Q - (double)(16 * k) * P;
+  r.lum = (2u * m[0] + (uint32_t)(B * B)) >> (LOGN + 1);
+  const double dm = (double)((int)(r.lum << LOGN) - (int)m[0]);
+  const double S = f + 64.0 * (r.R + dm * dm);
+  r.accept = S < thr64;
+  return r;
 }
 
 // Phase-2 contrast sets (twentieths) and mean-difference bounds per level

@@ -328,7 +328,7 @@ fe_status encode_geometry(fe_ctx* ctx, const fe_image_desc* imgs, uint32_t n_img
   fe_status st = build_table(imgs, n_imgs, p, g.shape, table, g.tiles, g.wgs);
   if (st != FE_OK) return st;
   g.chunks = (size_t)((g.tiles + kChunkTiles - 1) / kChunkTiles);
-  g.slots = (uint64_t)g.wgs * (uint64_t)(g.shape.gx * g.shape.gy) * (uint64_t)g.cells;
+  g.slots = (uint64_t)g.wgs * (uint64_t)(g.shape.gx * g.shape.gy) * (uint64_t)(g.cells + 1);
   g.fine_max = g.ext ? g.tiles * (uint64_t)(g.bmax / 4) * (uint64_t)(g.bmax / 4) : 0;
   // the 2 x 2 level's list names each child's record slot in 32 bits
   if (g.ext && g.slots >= (1ull << 32))
@@ -367,11 +367,12 @@ fe_status encode_launch(fe_ctx* ctx, const EncodeGeom& g, const EncodeBufs& b, u
       f.n_imgs = n_imgs;
       f.list = b.fine_list;
       f.count = b.fine_count;
-      f.gx = (uint32_t)g.shape.gx;
       f.level = (uint32_t)g.L;
       f.thr = p->mse_thr[g.L - 1];
       f.phase2 = a.phase2;
       f.identity_only = a.identity_only;
+      f.nt = (uint32_t)(g.shape.gx * g.shape.gy);
+      f.cells = (uint32_t)g.cells;
       f.staging = b.staging;
       f.masks = b.masks;
       FE_HIP(launch_fine_finish(f, g.fine_max, s), "2 x 2 level launch");
@@ -489,7 +490,7 @@ fe_status encode_full_search(fe_ctx* ctx, const uint8_t* d_img, uint32_t w, uint
   if ((st = ensure(ctx->fs_planes, ctx->fs_planes_n, pl0.plane_bytes, "phase planes")) != FE_OK) return st;
   for (int b = 0; b < 2; ++b)
     if ((st = ensure(ctx->fs_xy[b], ctx->fs_xy_n[b], max_ranges, "range lists")) != FE_OK) return st;
-  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * cells, "record staging")) != FE_OK) return st;
+  if ((st = ensure(ctx->staging, ctx->staging_n, (size_t)tiles * (cells + 1), "record staging")) != FE_OK) return st;
   if ((st = ensure(ctx->masks, ctx->masks_n, (size_t)tiles, "tile masks")) != FE_OK) return st;
   const size_t chunks = (size_t)((tiles + fe::kChunkTiles - 1) / fe::kChunkTiles);
   if ((st = ensure(ctx->chunk_sum, ctx->chunk_n, chunks, "chunk sums")) != FE_OK) return st;

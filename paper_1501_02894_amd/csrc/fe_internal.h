@@ -116,10 +116,12 @@ struct FinishArgs {
   uint32_t n_imgs;
   const uint4* list;
   const uint32_t* count;
-  uint32_t gx;          // record-slot stride between a range's children
   uint32_t level;       // 1-based level of the listed 4 x 4 ranges
   uint32_t thr;         // their MSE threshold (phase 2)
   uint32_t phase2, identity_only;
+  // record slots per block: nt whole-tile slots, then cells per tile (a
+  // listed range that is a whole tile stores its phase-2 record in the former)
+  uint32_t nt, cells;
   uint4* staging;
   uint64_t* masks;
 };

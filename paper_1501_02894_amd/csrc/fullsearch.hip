@@ -471,7 +471,8 @@ __global__ __launch_bounds__(256) void fs_finalize_kernel(FsGeo g, const uint8_t
     for (int bit = 0; bit < 3; ++bit) cell |= (((lx >> bit) & 1u) << (2 * bit)) | (((ly >> bit) & 1u) << (2 * bit + 1));
     const uint32_t L = 31 - __builtin_clz(b_max / b_min) + 1;
     const uint64_t tile = (uint64_t)ty * tiles_x + tx;
-    staging[tile * (1ull << (2 * (L - 1))) + cell] =
+    // slots of one-tile blocks: the whole-tile record, then one per cell
+    staging[tile * ((1ull << (2 * (L - 1))) + 1) + (B == b_max ? 0u : 1u + cell)] =
         make_record((int)x, (int)y, (int)du, (int)dv, level - 1, 0, e, k, (int)m, 0, 0, 0);
     atomicOr(&masks[tile], 1ull << cell);
   } else {

@@ -9,19 +9,20 @@
 //      H0 of that region and its transpose are formed in LDS on the fly
 //      (Sec. 3, the four-neighbour mean filter).
 //   2. per level l (B = B_max >> (l-1)), the workgroup's list of ranges is
-//      cut into passes of 64 lanes, a team of T lanes per range, and the
-//      passes are dealt round the four waves: the team sums packed-u8 dot
-//      products (v_dot4_u32_u8)
-//      over row pairs of the range and of the domain window / its transpose,
-//      giving Sum r, Sum r^2, Sum d, Sum d^2 and the 8 isometric Sum r T_e(d);
-//      a DPP butterfly leaves the totals in every lane, and every lane fits
-//      (e, k, m) exactly in fp64 (Sec. 3).
-//   3. phase 2 (Sec. 3.1-3.3): in the same pass, the parents that failed at
+//      fitted one range per lane: sums of packed-u8 dot products
+//      (v_dot4_u32_u8) over row pairs of the range and of the domain window
+//      / its transpose give Sum r, Sum r^2, Sum d, Sum d^2 and the 8
+//      isometric Sum r T_e(d), and the lane fits (e, k, m) exactly in fp64
+//      (Sec. 3).  Long lists are dealt round the waves in groups of 64;
+//      a list of at most 64 ranges has its rows spread over the waves, whose
+//      partial sums meet in LDS before one wave fits it.
+//   3. phase 2 (Sec. 3.1-3.3): in the same lanes, the parents that failed at
 //      level l-1 are decided from the identity moments of their four
-//      children, which are exactly the level-l ranges just computed.
+//      children, which are exactly the level-l ranges just computed (four
+//      consecutive lanes, exchanged by DPP).
 //   4. accepted ranges are written as 16-byte records into per-tile slots
 //      indexed by the Morton code of their top-left B_min cell; failed ranges
-//      are compacted (wave ballot + prefix, one LDS atomic per pass) into the
+//      are compacted (wave ballot + prefix, one LDS atomic per wave) into the
 //      workgroup's parent list, which every wave reads after a barrier: entry
 //      e of the next level is child e mod 4 (Z order) of parent e / 4.
 //
@@ -39,6 +40,7 @@ namespace {
 template <int BMAX, int L, int GX, int GY>
 struct Geo {
   static constexpr int BMAXV = BMAX;
+  static constexpr int GXV = GX;
   static constexpr int BMIN = BMAX >> (L - 1);
   static constexpr int NT = GX * GY;                          // tiles per workgroup
   static constexpr int LOG_GX = Log2<GX>::value;
@@ -46,13 +48,17 @@ struct Geo {
   // failed ranges of one level, at most NT 4^(L-2) (level L-1)
   static constexpr int PCAP = NT * CELLS / 4 > 0 ? NT * CELLS / 4 : 1;
   static constexpr int TW = GX * BMAX, TH = GY * BMAX;        // tile block in pixels
-  static constexpr int TPITCH = TW + 4;                       // tile pixel row pitch (bytes)
+  // Tile pixels in LDS tile after tile, each tile row-major (pitch BMAX
+  // bytes), tiles TSTRIDE bytes apart: one dword more than a tile, so that
+  // the same row of different tiles falls in different banks.
+  static constexpr int TPITCH = BMAX;                         // tile pixel row pitch (bytes)
+  static constexpr int TSTRIDE = BMAX * BMAX + 4;             // tile stride (bytes)
   static constexpr int RWA = ((GX + 1) * BMAX + 6 + 7) & ~7;  // region width bound (px)
   static constexpr int RHA = (GY + 1) * BMAX + 8;             // region height bound (px)
   static constexpr int HW = RWA / 2, HH = RHA / 2;            // H0 region bounds
   static constexpr int HP = HW + 8;                           // H0 row pitch
   static constexpr int TP = ((HH + 3) & ~3) + 8;              // H0^T row pitch
-  static constexpr int IMG_W = TH * TPITCH / 4 + 4;           // dwords
+  static constexpr int IMG_W = NT * TSTRIDE / 4 + 4;          // dwords
   static constexpr int HH4 = (HH + 3) & ~3;                   // H0 rows, multiple of 4
   static constexpr int H0_W = HH4 * HP / 4 + 4;
   static constexpr int H0T_W = HW * TP / 4 + 4;
@@ -66,37 +72,6 @@ struct Region {
   int tiles_x;
   uint64_t tg0;        // global index of the block's first tile
 };
-
-// List entry: bits 0-7 cell x, 8-15 cell y (in B_min units inside the tile),
-// bits 16+ tile index t = tly * GX + tlx inside the workgroup's block.
-template <int BMAX, int BMIN, int LOG_GX>
-__device__ __forceinline__ void range_xy(uint32_t meta, const Region& r, int& X, int& Y) {
-  const int t = (int)(meta >> 16);
-  X = r.X0 + (t & ((1 << LOG_GX) - 1)) * BMAX + (int)(meta & 0xffu) * BMIN;
-  Y = r.Y0 + (t >> LOG_GX) * BMAX + (int)((meta >> 8) & 0xffu) * BMIN;
-}
-
-template <int LOG_GX>
-__device__ __forceinline__ uint64_t tile_global(uint32_t meta, const Region& r) {
-  const int t = (int)(meta >> 16);
-  return r.tg0 + (uint64_t)((uint32_t)(t >> LOG_GX) * (uint32_t)r.tiles_x + (uint32_t)(t & ((1 << LOG_GX) - 1)));
-}
-
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-
-__device__ __forceinline__ int morton(uint32_t meta) {
-  const int cx = meta & 0xff, cy = (meta >> 8) & 0xff;
-  int code = 0;
-#pragma unroll
-  for (int bit = 0; bit < 3; ++bit) {
-    code |= ((cx >> bit) & 1) << (2 * bit);
-    code |= ((cy >> bit) & 1) << (2 * bit + 1);
-  }
-  return code;
-}
 
 // Geometry of one block of top tiles and of its staged region.
 struct BlockGeo {
@@ -145,22 +120,27 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 
 // Region staging.  A group is 8 x 8 pixels of the region (column group c8,
 // rows 8 g .. 8 g + 7), i.e. a 4 x 4 block of H0; lane `tid` owns groups
-// tid + 256 * it.  H0 is written as dwords, and its transpose as dwords
-// after a 4 x 4 byte transpose in registers.
+// tid + 256 * it.  load() reads the lane's groups from the image into
+// registers; store() writes them to LDS: the tile pixels, H0 as dwords, and
+// its transpose as dwords after a 4 x 4 byte transpose in registers.
 template <class G>
 struct Stage {
   static constexpr int NC8 = G::RWA / 8;
   static constexpr int NG = (G::HH4 / 4 * NC8 + 255) / 256;
+  uint32_t v[NG][8][2];
 
-  __device__ __forceinline__ static void run(const BlockGeo& b, int tid, uint32_t* s_img, uint32_t* s_h0,
-                                             uint32_t* s_h0t) {
+  __device__ __forceinline__ static bool owns(const BlockGeo& b, int idx, int& g, int& c8) {
+    g = idx / NC8;
+    c8 = idx - g * NC8;
+    return 4 * g < b.hrows && c8 < b.n8;
+  }
+
+  __device__ __forceinline__ void load(const BlockGeo& b, int tid) {
 #pragma unroll
     for (int it = 0; it < NG; ++it) {
-      const int idx = tid + 256 * it;
-      const int g = idx / NC8, c8 = idx - g * NC8;
-      if (4 * g >= b.hrows || c8 >= b.n8) continue;
+      int g, c8;
+      if (!owns(b, tid + 256 * it, g, c8)) continue;
       const int x = b.rg.ax0 + 8 * c8;
-      uint32_t v[8][2];
       const uint8_t* row0 = b.data + (size_t)(b.rg.ay0 + 8 * g) * b.stride + x;
       if constexpr (G::BMAXV >= 16) {
         // the region spans multiples of 8 pixels inside the image in both
@@ -168,24 +148,35 @@ struct Stage {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const gu32* p = (const gu32*)(row0 + (size_t)r * b.stride);
-          v[r][0] = p[0];
-          v[r][1] = p[1];
+          v[it][r][0] = p[0];
+          v[it][r][1] = p[1];
         }
       } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-          v[r][0] = v[r][1] = 0u;
+          v[it][r][0] = v[it][r][1] = 0u;
           if (8 * g + r < 2 * b.hrows) {
             const gu32* p = (const gu32*)(row0 + (size_t)r * b.stride);
             if (x + 8 <= b.rg.W) {
-              v[r][0] = p[0];
-              v[r][1] = p[1];
+              v[it][r][0] = p[0];
+              v[it][r][1] = p[1];
             } else if (x < b.rg.W) {
-              v[r][0] = p[0];
+              v[it][r][0] = p[0];
             }
           }
         }
       }
+    }
+  }
+
+  __device__ __forceinline__ void store(const BlockGeo& b, int tid, uint32_t* s_img, uint32_t* s_h0,
+                                        uint32_t* s_h0t) const {
+#pragma unroll
+    for (int it = 0; it < NG; ++it) {
+      int g, c8;
+      if (!owns(b, tid + 256 * it, g, c8)) continue;
+      const int x = b.rg.ax0 + 8 * c8;
+      const uint32_t(&w)[8][2] = v[it];
       // tile pixels.  For b_max >= 8 the tile block starts at a multiple of
       // 8 pixels from the region origin in both directions and spans a
       // multiple of 8, so a group lies wholly inside or outside it; for
@@ -193,14 +184,17 @@ struct Stage {
       if constexpr (G::BMAXV >= 8) {
         const int gy0 = b.rg.ay0 + 8 * g;
         if (gy0 >= b.rg.Y0 && gy0 < b.ty_end && x >= b.rg.X0 && x < b.tx_end) {
-          uint32_t* dst = s_img + (gy0 - b.rg.Y0) * (G::TPITCH / 4) + ((x - b.rg.X0) >> 2);
+          const int px = x - b.rg.X0, py = gy0 - b.rg.Y0;   // inside the tile block
+          const int t = (py / G::BMAXV) * G::GXV + px / G::BMAXV;
+          uint32_t* dst = s_img + t * (G::TSTRIDE / 4) + (py % G::BMAXV) * (G::TPITCH / 4) + (px % G::BMAXV) / 4;
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
-            dst[r * (G::TPITCH / 4)] = v[r][0];
-            dst[r * (G::TPITCH / 4) + 1] = v[r][1];
+            dst[r * (G::TPITCH / 4)] = w[r][0];
+            dst[r * (G::TPITCH / 4) + 1] = w[r][1];
           }
         }
       } else {
+        // 4 x 4 tiles: one row of four pixels per tile and dword
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int y = b.rg.ay0 + 8 * g + r;
@@ -208,8 +202,10 @@ struct Stage {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int xx = x + 4 * h;
-            if (xx >= b.rg.X0 && xx < b.tx_end)
-              s_img[(y - b.rg.Y0) * (G::TPITCH / 4) + ((xx - b.rg.X0) >> 2)] = v[r][h];
+            if (xx >= b.rg.X0 && xx < b.tx_end) {
+              const int t = ((y - b.rg.Y0) >> 2) * G::GXV + ((xx - b.rg.X0) >> 2);
+              s_img[t * (G::TSTRIDE / 4) + ((y - b.rg.Y0) & 3)] = w[r][h];
+            }
           }
         }
       }
@@ -217,7 +213,7 @@ struct Stage {
       uint32_t hrow[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        hrow[q] = mean2x2_x4(v[2 * q][0], v[2 * q][1], v[2 * q + 1][0], v[2 * q + 1][1]);
+        hrow[q] = mean2x2_x4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]);
         s_h0[(4 * g + q) * (G::HP / 4) + c8] = hrow[q];
       }
       // transpose the 4x4 byte block: H0T rows 4 c8 .. 4 c8 + 3, columns 4g..
@@ -240,78 +236,103 @@ struct Lds {
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
   uint32_t top[G::NT];             // level-1 list: the block's tiles inside the image
-  uint32_t par[2][G::PCAP];        // failed ranges of two consecutive levels, meta | m << 24
+  uint32_t par[2][G::PCAP];        // failed ranges of two consecutive levels (list entries)
+  uint32_t part[12][64];           // moments of a short list, summed over the waves
   uint32_t cnt[L + 1];             // per level: ranges that failed (parents of the next list)
   unsigned long long mask[G::NT];
 };
 
-// Lane `src` of the wave's value v.
-__device__ __forceinline__ int lane_read(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
-
-// VALU instructions of one level pass of the compiled kernel by range side:
-// per moment iteration (one row pair of a range per lane) and per pass (the
-// fits, phase 2, record stores and compaction, whatever T is).
-template <int BB>
-struct PassCost;
-template <>
-struct PassCost<32> { static constexpr int it = 250, pass = 220; };
-template <>
-struct PassCost<16> { static constexpr int it = 127, pass = 200; };
-template <>
-struct PassCost<8> { static constexpr int it = 79, pass = 300; };
-template <>
-struct PassCost<4> { static constexpr int it = 49, pass = 280; };
-
-// Team size T (lanes per range, a power of two up to min(BB/2, 16)) for a
-// workgroup list of n ranges of side BB.  The top level splits its tiles
-// evenly over the four waves and fills their lanes.  Lower levels take the T
-// of least VALU work in total, ceil(n T / 64) passes of ceil(BB / 2T)
-// moment iterations plus the per-pass work: small teams when the list is
-// long, large ones when a short list would otherwise leave lanes idle.
-template <int BB>
-__device__ __forceinline__ int team_size(int n, bool top) {
-  constexpr int TMAX = BB / 2 < 16 ? BB / 2 : 16;
-  if (top) {
-    const int nw = (n + 3) >> 2;
-    int T = 1;
-    while (T < TMAX && nw * T * 2 <= 64) T *= 2;
-    return T;
-  }
-  int best_t = 1, best = 0x7fffffff;
-  for (int T = 1, lg = 0; T <= TMAX; T *= 2, ++lg) {
-    const int c = ((n * T + 63) >> 6) * ((BB / 2 + T - 1) / T * PassCost<BB>::it + PassCost<BB>::pass + 12 * lg);
-    if (c < best) {
-      best = c;
-      best_t = T;
-    }
-  }
-  return best_t;
+// DPP: every lane of a quad reads quad lane Q's value, or the sum over its quad.
+template <int Q>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, Q * 0x55, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int quad_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  return v + __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
 }
 
-// The quadtree of one block, the four waves sharing each level's list.  Uses
-// only LDS data staged for the block; writes records to staging and tile
-// masks.
+// A range of the list: its place inside the workgroup's block of tiles.
+// List entries hold x | y << 8 (pixels from the block's first tile) | the
+// Morton code of its top-left B_min cell inside its tile << 16, and in the
+// lists of failed ranges also its phase-1 mean m << 24.  Entry e of a level
+// below the top is child e mod 4 (Z order) of failed range e / 4 above.
+struct RangeRef {
+  int xr, yr;   // relative to the block's first tile
+  int cell;     // Morton code of the top-left B_min cell in its tile
+  int m;        // the parent's mean (levels below the top)
+};
+
+template <int BB, int BMAX, int BMIN>
+__device__ __forceinline__ RangeRef range_ref(const uint32_t* top, const uint32_t* ppar, int e) {
+  RangeRef r;
+  if constexpr (BB == BMAX) {
+    const uint32_t t = top[e];
+    r.xr = (int)(t & 0xffu);
+    r.yr = (int)((t >> 8) & 0xffu);
+    r.cell = 0;
+    r.m = 0;
+  } else {
+    constexpr int CL = (BB / BMIN) * (BB / BMIN);   // cells covered by one range of this level
+    const uint32_t pe = ppar[e >> 2];
+    const int c = e & 3;
+    r.xr = (int)(pe & 0xffu) + (c & 1) * BB;
+    r.yr = (int)((pe >> 8) & 0xffu) + (c >> 1) * BB;
+    r.cell = (int)((pe >> 16) & 0xffu) + c * CL;
+    r.m = (int)(pe >> 24);
+  }
+  return r;
+}
+
+// LDS offsets of a range's pixels, of its co-centred domain window in H0
+// and of that window in H0^T.
+template <class G, int BB>
+struct Window {
+  int dx, dy;            // domain origin (pixels, in the image)
+  int roff, doff, toff;
+  __device__ __forceinline__ Window(const RangeRef& r, const Region& rg) {
+    dx = clampi(rg.X0 + r.xr - BB / 2, 0, rg.W - 2 * BB);
+    dy = clampi(rg.Y0 + r.yr - BB / 2, 0, rg.H - 2 * BB);
+    const int wx = (dx - rg.ax0) >> 1, wy = (dy - rg.ay0) >> 1;
+    constexpr int LB = Log2<G::BMAXV>::value;
+    roff = ((r.yr >> LB) * G::GXV + (r.xr >> LB)) * G::TSTRIDE + (r.yr & (G::BMAXV - 1)) * G::TPITCH +
+           (r.xr & (G::BMAXV - 1));
+    doff = wy * G::HP + wx;
+    toff = wx * G::TP + wy;
+  }
+};
+
+// Record slot, inside its block's slots, of the record at Morton cell
+// `cell` (record-cell units) of the tile at column tx, row ty of the block:
+// a record that covers the whole tile goes to the block's first NT slots
+// (tile after tile, so that the many unsplit tiles of an image fill whole
+// lines), the records of a split tile to that tile's own CE slots after
+// them, indexed by cell (so a split tile's records share lines too).
+template <int GX, int NT, int CE>
+__device__ __forceinline__ uint32_t rec_slot(int tx, int ty, int cell, bool whole) {
+  const uint32_t t = (uint32_t)ty * GX + (uint32_t)tx;
+  return whole ? t : (uint32_t)NT + t * (uint32_t)CE + (uint32_t)cell;
+}
+
+// The quadtree of one block, the four waves sharing each level's list.
+// Uses only LDS data staged for the block; writes records to staging and
+// tile masks.
 //
-// Per level the list is cut into passes of 64 lanes, a team of T lanes per
-// range, and pass p goes to wave (p + rot) mod 4: the team accumulates the
-// range's moments and reduces them so that every lane of the team holds the
-// totals; every lane then fits the range.  From level 2 on the list holds
-// the four children (Z order) of each range that failed the level above, in
-// consecutive teams of one pass (4T divides 64), so the same pass also runs
-// the parent's phase 2 (Technique 1) across the four teams.  Accepted ranges
-// are written at once; failed ones are compacted (ballot prefix, one LDS
-// atomic per pass) into the parent list of the next level, whose entry e is
-// then child e mod 4 of parent e / 4.  A barrier ends each level.
-// Record slot of Morton cell `cell` of tile t (row-major in a block of GX
-// tiles per row) inside its block: one row of the block's tiles at a time,
-// and inside a row cell-major, so that the records of one cell of a tile
-// row are adjacent (the level pass writes them together) and a tile row's
-// records sit in one span (the ordering kernel reads them together).
-template <int GX>
-__device__ __forceinline__ uint32_t rec_slot(uint32_t t, int cell, int cells) {
-  return (t / GX) * (uint32_t)(GX * cells) + (uint32_t)cell * GX + t % GX;
-}
-
+// Every range is fitted by exactly one lane.  A level's moments come from
+// one of two layouts:
+//  - a list of more than 64 ranges is cut into groups of 64, dealt round the
+//    four waves; a lane sums every row of its range;
+//  - a list of at most 64 ranges is one group whose rows are spread over the
+//    waves (and, when the list is short, over teams of lanes inside each
+//    wave, reduced by DPP); the waves add their partial moments into LDS and,
+//    after a barrier, one wave fits the whole list, a lane per range.
+// The fit is phase 1 (Sec. 3); from level 2 on, the list holds the four
+// children (Z order) of each range that failed the level above in four
+// consecutive lanes, so the same lanes also decide the parent's Technique 1
+// (Sec. 3.1-3.3) by DPP exchanges inside their quad.  Accepted ranges are
+// written at once; failed ones are compacted (ballot prefix, one LDS atomic
+// per wave) into the parent list of the next level.  A barrier ends each
+// level.
 template <int BMAX, int L, int GX, int GY, bool EXT>
 __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm,
                                               uint32_t rot) {
@@ -320,163 +341,202 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
   // to 2 x 2 (EXT), whose Morton codes are those of the B_min cells times 4
   constexpr int CE = EXT ? 4 * G::CELLS : G::CELLS;
   constexpr int CSH = EXT ? 2 : 0;
+  constexpr int LOG_BMAX = Log2<BMAX>::value;
   const Region& rg = bg.rg;
-  const int gx = bg.gx, gy = bg.gy;
   const int tid = threadIdx.x;
-  const uint32_t* s_img = sm.img;
-  const uint32_t* s_h0 = sm.h0;
-  const uint32_t* s_h0t = sm.h0t;
+  const uint8_t* img_b = reinterpret_cast<const uint8_t*>(sm.img);
+  const uint8_t* h0_b = reinterpret_cast<const uint8_t*>(sm.h0);
+  const uint8_t* h0t_b = reinterpret_cast<const uint8_t*>(sm.h0t);
   unsigned long long* s_mask = sm.mask;
-  const uint64_t slot0 = (uint64_t)bg.sblk * (uint64_t)(G::NT * CE);   // the block's record slots
+  uint4* const rec_base = a.staging + (uint64_t)bg.sblk * (uint64_t)(G::NT * (CE + 1));   // the block's record slots
   const int wave = tid >> 6, lane = tid & 63;
-  const int p0 = (wave - (int)rot) & 3;   // this wave's first pass of a level
+  const int wr = (wave - (int)rot) & 3;   // this wave's rank in the block
 
   // ranges in the current list (workgroup-uniform); level 1: the block's
   // tiles inside the image, listed by the kernel before its barrier
-  int n = gx * gy;
+  int n = bg.gx * bg.gy;
   for (int lev = 1; lev <= L; ++lev) {
     const uint32_t* ppar = sm.par[(lev - 1) & 1];   // parents of this level's ranges
     uint32_t* npar = sm.par[lev & 1];               // this level's failed ranges
     uint32_t* nfail = &sm.cnt[lev];                 // zeroed by the kernel
     const bool last = lev == L && !EXT;   // EXT: the 4 x 4 level is tested too
-    const uint32_t thr = last ? 0u : a.thr[lev - 1];
     const int B = BMAX >> (lev - 1);
 
     auto level_pass = [&](auto bconst) {
       constexpr int BB = decltype(bconst)::value;
       constexpr bool ALIGNED = BB >= 16;
-      const int T = team_size<BB>(n, BB == BMAX);
-      const int logT = __builtin_ctz((unsigned)T);
-      const int passes = (n * T + 63) >> 6;
-      for (int p = p0; p < passes; p += 4) {
-        const int idx = p * 64 + lane;
-        const int e = idx >> logT, t = idx & (T - 1);
-        const bool valid = e < n;
-        // ---- moments of range e (the team's rows t, t + T, ...)
-        uint32_t acc[12];
-#pragma unroll
-        for (int j = 0; j < 12; ++j) acc[j] = 0u;
-        uint32_t meta = 0, pe = 0;
-        int X = 0, Y = 0;
-        if (valid) {
-          if constexpr (BB == BMAX) {
-            meta = sm.top[e];
-          } else {
-            // child e mod 4 (Z order) of the failed parent e / 4
-            constexpr uint32_t side = (uint32_t)(BB / G::BMIN);   // in B_min cells
-            pe = ppar[e >> 2];
-            const uint32_t c = (uint32_t)e & 3u;
-            meta = (pe & 0x00ff0000u) | ((((pe >> 8) & 0xffu) + (c >> 1) * side) << 8) | ((pe & 0xffu) + (c & 1u) * side);
-          }
-          range_xy<BMAX, G::BMIN, G::LOG_GX>(meta, rg, X, Y);
-          const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
-          const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
-          const int rx = X - rg.X0, ry = Y - rg.Y0;
-          const int wx = (dx - rg.ax0) >> 1, wy = (dy - rg.ay0) >> 1;
-          for (int i = t; i < BB / 2; i += T)
-            accumulate_row_pair<BB, ALIGNED>(s_img, ry * G::TPITCH + rx, G::TPITCH, s_h0, wy * G::HP + wx,
-                                             G::HP, s_h0t, wx * G::TP + wy, G::TP, i, acc);
-        }
-        team_reduce(acc, T);   // butterfly: every lane of the team holds the totals
-        if (a.identity_only) {  // every isometry scores as the identity: the fit keeps e = 0
+      constexpr int RP = BB / 2;                           // row pairs of a range
+      constexpr double NN = (double)(BB * BB);
+      using W = Window<G, BB>;
+      // 64 n^2 t of this level; a forced level accepts every range
+      const double thr64 = last ? __builtin_inf() : 64.0 * NN * NN * (double)a.thr[lev - 1];
+
+      // Fit, Technique 1, records and compaction for list entry e, lane =
+      // e mod 64, given the range's moments in acc.
+      auto finish = [&](int e, bool valid, uint32_t (&acc)[12]) {
+        const RangeRef r = range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1));
+        if (a.identity_only) {   // every isometry scores as the identity: the fit keeps e = 0
 #pragma unroll
           for (int j = 5; j < 12; ++j) acc[j] = acc[4];
         }
-        const uint32_t fit = fit_phase1<BB>(acc, last, thr);
+        const Fit1 f = fit_phase1_terms<BB>(acc, thr64);
+        const int tx = r.xr >> LOG_BMAX, ty = r.yr >> LOG_BMAX;
 
-        // ---- phase 2 of the parent of this group of four children
+        // ---- Technique 1 for the parent of this quad of children
         bool dead = false;   // the parent was stored by phase 2
         if constexpr (BB < BMAX) {
           if (a.phase2) {
             constexpr int LOGNB = 2 * Log2<BB>::value;
-            constexpr double NB = (double)(BB * BB);
             int c1, c2, delta;
             phase2_consts(lev - 1, c1, c2, delta);
-            const double thr2 = (400.0 * NB * NB) * (double)a.thr[lev - 2];
+            const double thr2 = 400.0 * NN * NN * (double)a.thr[lev - 2];
             const int c = e & 3;
-            const int g0 = lane - c * T;               // lane of child 0 (same t)
-            const int m = (int)(pe >> 24);
+            const int m = r.m;
             int O = (int)((2u * acc[0] + (uint32_t)(BB * BB)) >> (LOGNB + 1));
-            const int O0 = lane_read(O, g0), O1 = lane_read(O, g0 + T), O2 = lane_read(O, g0 + 2 * T);
+            const int O0 = quad_bcast<0>(O), O1 = quad_bcast<1>(O), O2 = quad_bcast<2>(O);
             if (c == 3) O = 4 * m - O0 - O1 - O2;   // eq. (1)
-            const double dsr = (double)acc[0], dsd = (double)acc[2];
-            const double Q = NB * (double)acc[3] - dsd * dsd;
-            const double P = NB * (double)acc[4] - dsr * dsd;
-            const double R = NB * (double)acc[1] - dsr * dsr;
-            const double f1 = (double)(c1 * c1) * Q - (double)(40 * c1) * P;
-            const double f2 = (double)(c2 * c2) * Q - (double)(40 * c2) * P;
+            const double P0 = NN * (double)acc[4] - f.srsd;
+            const double f1 = (double)(c1 * c1) * f.Q - (double)(40 * c1) * P0;
+            const double f2 = (double)(c2 * c2) * f.Q - (double)(40 * c2) * P0;
             const bool use2 = f2 < f1;
-            const double dm = (double)O * NB - dsr;
-            const double S = (use2 ? f2 : f1) + 400.0 * R + 400.0 * (dm * dm);
-            const bool okc = valid && O - m <= delta && m - O <= delta && O >= 0 && O <= 255 && S < thr2;
-            const uint64_t okb = __ballot(okc), u2b = __ballot(valid && use2);
-            const uint64_t pat = 1ull | (1ull << T) | (1ull << (2 * T)) | (1ull << (3 * T));
-            dead = valid && ((okb >> g0) & pat) == pat;
-            if (dead && c == 0 && t == 0) {
-              const uint64_t ub = u2b >> g0;
-              const int bits = (int)((ub & 1ull) | (((ub >> T) & 1ull) << 1) | (((ub >> (2 * T)) & 1ull) << 2) |
-                                     (((ub >> (3 * T)) & 1ull) << 3));
-              const uint32_t pmeta = pe & 0x00ffffffu;
-              int PX, PY;
-              range_xy<BMAX, G::BMIN, G::LOG_GX>(pmeta, rg, PX, PY);
+            const double dm = (double)(O * (BB * BB) - (int)acc[0]);
+            const double S = (use2 ? f2 : f1) + 400.0 * (f.R + dm * dm);
+            const bool okc = (uint32_t)(O - m + delta) <= (uint32_t)(2 * delta) && (uint32_t)O <= 255u && S < thr2;
+            const int all = quad_sum(okc ? 1 : 0);
+            const int bits = quad_sum((use2 ? 1 : 0) << c);
+            dead = valid && all == 4;
+            if (dead && c == 0) {
+              const int pxr = r.xr, pyr = r.yr;   // child 0 shares its parent's corner
               constexpr int PB = 2 * BB;
+              const int PX = rg.X0 + pxr, PY = rg.Y0 + pyr;
               const int pdx = clampi(PX - PB / 2, 0, rg.W - 2 * PB);
               const int pdy = clampi(PY - PB / 2, 0, rg.H - 2 * PB);
-              const int cell = morton(pmeta) << CSH;
-              a.staging[slot0 + rec_slot<GX>((pmeta >> 16) & 0xffu, cell, CE)] =
+              const int cell = r.cell << CSH;
+              rec_base[rec_slot<GX, G::NT, CE>(tx, ty, cell, PB == BMAX)] =
                   make_record(PX, PY, pdx, pdy, lev - 2, 1, 0, bits, m, O0 - m, O1 - m, O2 - m);
-              atomicOr(&s_mask[pmeta >> 16], 1ull << cell);
+              atomicOr(&s_mask[ty * GX + tx], 1ull << cell);
             }
           }
         }
 
-        // ---- store accepted ranges; compact failures into the next lists
-        const bool lead = valid && t == 0 && !dead;
-        bool fail = false;
-        if (lead) {
-          if (fit & kFitAccept) {
-            const int dx = clampi(X - BB / 2, 0, rg.W - 2 * BB);
-            const int dy = clampi(Y - BB / 2, 0, rg.H - 2 * BB);
-            const int cell = morton(meta) << CSH;
-            a.staging[slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, CE)] =
-                make_record(X, Y, dx, dy, lev - 1, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
-                            (int)(fit & 0xffu), 0, 0, 0);
-            atomicOr(&s_mask[meta >> 16], 1ull << cell);
-          } else {
-            fail = true;
-          }
+        // ---- store accepted ranges; compact failures into the next list
+        const bool live = valid && !dead;
+        const bool fail = live && !f.accept;
+        if (live && f.accept) {
+          const W w(r, rg);
+          const int cell = r.cell << CSH;
+          rec_base[rec_slot<GX, G::NT, CE>(tx, ty, cell, BB == BMAX)] = make_record(rg.X0 + r.xr, rg.Y0 + r.yr, w.dx, w.dy, lev - 1, 0,
+                                                                 (int)f.e, (int)f.k, (int)f.lum, 0, 0, 0);
+          atomicOr(&s_mask[ty * GX + tx], 1ull << cell);
         }
         const uint64_t bal = __ballot(fail);
+        if (!bal) return;
+        const int first = (int)__builtin_ctzll(bal);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        const uint32_t ent = (uint32_t)r.xr | ((uint32_t)r.yr << 8) | ((uint32_t)r.cell << 16);
         if constexpr (EXT) {
           if (lev == L) {
             // failed 4 x 4 ranges go on to the 2 x 2 level, through the
             // global list (one atomic per wave)
-            if (bal) {
-              const int first = (int)__builtin_ctzll(bal);
-              uint32_t base = 0;
-              if (lane == first) base = atomicAdd(a.fine_count, (uint32_t)__popcll(bal));
-              base = (uint32_t)__shfl((int)base, first);
-              if (fail) {
-                const uint32_t q = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                const int cell = morton(meta) << CSH;
-                a.fine_list[q] = make_uint4((uint32_t)X | ((uint32_t)Y << 16),
-                                            (uint32_t)(slot0 + rec_slot<GX>((meta >> 16) & 0xffu, cell, CE)),
-                                            (uint32_t)tile_global<G::LOG_GX>(meta, rg),
-                                            (fit & 0xffu) | ((uint32_t)cell << 8));
-              }
+            uint32_t base = 0;
+            if (lane == first) base = atomicAdd(a.fine_count, (uint32_t)__popcll(bal));
+            base = (uint32_t)__shfl((int)base, first);
+            if (fail) {
+              const int cell = r.cell << CSH;
+              const uint64_t tg = rg.tg0 + (uint64_t)((uint32_t)ty * (uint32_t)rg.tiles_x + (uint32_t)tx);
+              a.fine_list[base + rank] =
+                  make_uint4((uint32_t)(rg.X0 + r.xr) | ((uint32_t)(rg.Y0 + r.yr) << 16),
+                             (uint32_t)((rec_base - a.staging) + rec_slot<GX, G::NT, CE>(tx, ty, cell, false)), (uint32_t)tg,
+                             f.lum | ((uint32_t)cell << 8));
             }
-            continue;
+            return;
           }
         }
-        if (bal) {
-          const int first = (int)__builtin_ctzll(bal);
-          uint32_t q0 = 0;
-          if (lane == first) q0 = atomicAdd(nfail, (uint32_t)__popcll(bal));
-          q0 = (uint32_t)__shfl((int)q0, first);
-          if (fail)
-            npar[q0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
-                meta | ((fit & 0xffu) << 24);
+        uint32_t q0 = 0;
+        if (lane == first) q0 = atomicAdd(nfail, (uint32_t)__popcll(bal));
+        q0 = (uint32_t)__shfl((int)q0, first);
+        if (fail) npar[q0 + rank] = ent | (f.lum << 24);
+      };
+
+      // A short list has its rows spread over the waves at the top level
+      // (every block starts with one) and for ranges of 16 x 16 and larger;
+      // smaller ranges take too few rows for the split to pay.
+      constexpr bool TOP_SHORT = BB == BMAX && G::NT <= 64 && BB >= 8;
+      constexpr bool SPLIT_OK = BB >= 8 && (BB == BMAX || BB >= 16);
+      if (!TOP_SHORT && (n > 64 || !SPLIT_OK)) {
+        // groups of 64 ranges, one lane per range over all its rows (lanes
+        // beyond the list repeat its last range and store nothing)
+        for (int g = wr; g * 64 < n; g += 4) {
+          const int e = g * 64 + lane;
+          const bool valid = e < n;
+          const W w(range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1)), rg);
+          const uint8_t* r0 = img_b + w.roff;
+          const uint8_t* d0 = h0_b + w.doff;
+          const uint8_t* t0 = h0t_b + w.toff;
+          uint32_t acc[12];
+#pragma unroll
+          for (int j = 0; j < 12; ++j) acc[j] = 0u;
+          // small ranges unrolled whole; larger ones a row pair at a time
+          // (their loads would otherwise all be hoisted into registers)
+          if constexpr (RP <= 2) {
+#pragma unroll
+            for (int i = 0; i < RP; ++i)
+              accumulate_rows<BB, ALIGNED>(r0 + i * G::TPITCH, r0 + (BB - 1 - i) * G::TPITCH, d0 + i * G::HP,
+                                           d0 + (BB - 1 - i) * G::HP, t0 + i * G::TP, t0 + (BB - 1 - i) * G::TP, acc);
+          } else {
+#pragma unroll 1
+            for (int i = 0; i < RP; ++i)
+              accumulate_rows<BB, ALIGNED>(r0 + i * G::TPITCH, r0 + (BB - 1 - i) * G::TPITCH, d0 + i * G::HP,
+                                           d0 + (BB - 1 - i) * G::HP, t0 + i * G::TP, t0 + (BB - 1 - i) * G::TP, acc);
+          }
+          finish(e, valid, acc);
+        }
+      } else {
+        // one short list: rows spread over sw waves and over teams of tin
+        // lanes (tin x sw <= RP, powers of two), partial sums added in LDS
+        int p2 = 1;
+        while (p2 < n) p2 <<= 1;
+        const int tin = min(RP, 64 / p2);
+        const int sw = min(4, RP / tin);
+        if (wr < sw) {
+          const int logt = __builtin_ctz((unsigned)tin);
+          const int e = lane >> logt, t = lane & (tin - 1);
+          const W w(range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1)), rg);
+          const int i0 = wr * tin + t, step = sw * tin;
+          const uint8_t* ra = img_b + w.roff + i0 * G::TPITCH;
+          const uint8_t* rb = img_b + w.roff + (BB - 1 - i0) * G::TPITCH;
+          const uint8_t* da = h0_b + w.doff + i0 * G::HP;
+          const uint8_t* db = h0_b + w.doff + (BB - 1 - i0) * G::HP;
+          const uint8_t* ta = h0t_b + w.toff + i0 * G::TP;
+          const uint8_t* tb = h0t_b + w.toff + (BB - 1 - i0) * G::TP;
+          uint32_t acc[12];
+#pragma unroll
+          for (int j = 0; j < 12; ++j) acc[j] = 0u;
+          for (int i = i0; i < RP; i += step) {
+            accumulate_rows<BB, ALIGNED>(ra, rb, da, db, ta, tb, acc);
+            ra += step * G::TPITCH;
+            rb -= step * G::TPITCH;
+            da += step * G::HP;
+            db -= step * G::HP;
+            ta += step * G::TP;
+            tb -= step * G::TP;
+          }
+          team_reduce(acc, tin);
+          if (e < n && t == 0) {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) atomicAdd(&sm.part[j][e], acc[j]);
+          }
+        }
+        __syncthreads();   // the list's moments are complete
+        if (wr == 0) {
+          const bool valid = lane < n;
+          uint32_t acc[12];
+#pragma unroll
+          for (int j = 0; j < 12; ++j) {
+            acc[j] = sm.part[j][lane];   // zero beyond the list
+            sm.part[j][lane] = 0u;       // zero again for the next short list
+          }
+          finish(lane, valid, acc);
         }
       }
     };
@@ -491,8 +551,24 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
 
   // ---- publish the block's tiles' occupancy masks (complete after the
   // barrier that ended the last level)
-  for (int t = tid; t < G::NT; t += 256)
-    if ((t & (GX - 1)) < gx && (t >> G::LOG_GX) < gy) a.masks[tile_global<G::LOG_GX>((uint32_t)t << 16, rg)] = s_mask[t];
+  for (int t = tid; t < G::NT; t += 256) {
+    const int tx = t & (GX - 1), ty = t >> G::LOG_GX;
+    if (tx < bg.gx && ty < bg.gy)
+      a.masks[rg.tg0 + (uint64_t)((uint32_t)ty * (uint32_t)rg.tiles_x + (uint32_t)tx)] = s_mask[t];
+  }
+}
+
+template <int BMAX, int L, int GX, int GY>
+__device__ __forceinline__ void block_start(const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm, int tid) {
+  using G = Geo<BMAX, L, GX, GY>;
+  for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
+  for (int t = tid; t < 12 * 64; t += 256) (&sm.part[0][0])[t] = 0u;
+  if (tid <= L) sm.cnt[tid] = 0u;
+  // level-1 list: the block's tiles inside the image, row-major (gx gy <= NT <= 256)
+  if (tid < bg.gx * bg.gy) {
+    const int ty = tid / bg.gx, tx = tid - ty * bg.gx;
+    sm.top[tid] = (uint32_t)(tx * BMAX) | ((uint32_t)(ty * BMAX) << 8);
+  }
 }
 
 template <int BMAX, int L, int GX, int GY, bool EXT>
@@ -505,11 +581,10 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   const uint32_t wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   if (wg >= a.n_wg) return;
   const BlockGeo bg = block_geo<BMAX, GX, GY>(a.blocks[wg]);
-  Stage<G>::run(bg, tid, sm.img, sm.h0, sm.h0t);
-  for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
-  if (tid <= L) sm.cnt[tid] = 0u;
-  // level-1 list: the block's tiles inside the image, row-major (gx gy <= NT <= 256)
-  if (tid < bg.gx * bg.gy) sm.top[tid] = (uint32_t)((tid / bg.gx) * GX + tid % bg.gx) << 16;
+  Stage<G> st;
+  st.load(bg, tid);
+  st.store(bg, tid, sm.img, sm.h0, sm.h0t);
+  block_start(bg, sm, tid);
   __syncthreads();
   process_block<BMAX, L, GX, GY, EXT>(a, bg, sm, wg & 3u);
 }

@@ -102,11 +102,19 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
       dead = fit_phase2<2>(mom, m, (int)a.level, a.thr, O, bits);
     }
     if (dead) {
+      // a listed range that is a whole top tile (trees 4 -> 2) keeps its
+      // record in its block's whole-tile slot, not at its first child's
+      uint64_t pslot = ent.y;
+      if (a.level == 1) {
+        const uint64_t per = (uint64_t)a.nt * (a.cells + 1u);
+        const uint64_t blk = pslot / per;
+        pslot = blk * per + (pslot - blk * per - a.nt) / a.cells;
+      }
       if (c == 0)
-        a.staging[ent.y] = make_record(px, py, clampi(px - 2, 0, W - 8), clampi(py - 2, 0, H - 8), (int)a.level - 1,
+        a.staging[pslot] = make_record(px, py, clampi(px - 2, 0, W - 8), clampi(py - 2, 0, H - 8), (int)a.level - 1,
                                        1, 0, (int)bits, m, O[0] - m, O[1] - m, O[2] - m);
     } else {
-      a.staging[(uint64_t)ent.y + (uint64_t)c * a.gx] =
+      a.staging[(uint64_t)ent.y + (uint64_t)c] =
           make_record(cx, cy, ox, oy, (int)a.level, 0, (int)((fit >> 11) & 7u), (int)((fit >> 8) & 7u),
                       (int)(fit & 0xffu), 0, 0, 0);
     }

@@ -158,6 +158,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   if (!chunk_base) base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
   const int nt = gx * gy;
   unsigned long long m = 0ull, slot = 0ull;
+  uint32_t stride = 0;   // slots between cells of the tile
   if (has_tile) {
     m = m_raw;
     // the tile's image: the last of the chunk's images starting at or before it
@@ -167,10 +168,12 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
     const uint32_t ty = local / s_tx[k], tx = local - ty * s_tx[k];
     const uint32_t by = ty / (uint32_t)gy, bx = tx / (uint32_t)gx;
     const uint64_t blk = (uint64_t)s_wf[k] + (uint64_t)by * s_gx[k] + bx;
-    // slot of cell 0 (the block's slots hold one tile row after another,
-    // each cell-major: cell c of this tile at + c * gx)
-    slot = blk * (uint64_t)nt * (uint64_t)cells + (uint64_t)(ty - by * (uint32_t)gy) * (uint64_t)(gx * cells) +
-           (tx - bx * (uint32_t)gx);
+    // the block's slots: one whole-tile slot per tile, then each tile's
+    // cells; a tile whose only record covers it (mask 1) uses the former
+    const uint64_t t = (uint64_t)(ty - by * (uint32_t)gy) * (uint64_t)gx + (tx - bx * (uint32_t)gx);
+    const uint64_t blk0 = blk * (uint64_t)nt * (uint64_t)(cells + 1);
+    slot = m == 1ull ? blk0 + t : blk0 + (uint64_t)nt + t * (uint64_t)cells;
+    stride = m == 1ull ? 0u : 1u;
   }
   const uint32_t cnt = (uint32_t)__popcll(m);
   // exclusive scan of the counts over the 256 lanes
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
       uint32_t r = pos;
       for (; r < r0; ++r) mm &= mm - 1;
       for (; mm && r < r0 + kPass; ++r) {
-        s_rslot[r - r0] = slot + (unsigned long long)__builtin_ctzll(mm) * (unsigned long long)gx;
+        s_rslot[r - r0] = slot + (unsigned long long)__builtin_ctzll(mm) * stride;
         mm &= mm - 1;
       }
     }

@@ -110,7 +110,9 @@ struct Request {
   bool waited = false;                   // compute stream already waits on the copy event
   ReqState state = ReqState::Queued;
   size_t n_out = 0;
-  Clock::time_point t_submit, t_done;
+  // submitted, admitted (image copy issued), first and last step launched,
+  // found complete
+  Clock::time_point t_submit, t_admit, t_first, t_last, t_done;
   fe_status error = FE_OK;
 };
 
@@ -214,6 +216,7 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
       break;
     }
     s->queued.pop_front();
+    r->t_admit = Clock::now();
     r->dev_off = off;
     r->dev_len = need;
     r->img_off = off;
@@ -278,6 +281,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     if (!r->waited) {
       first_time.push_back(r);
       r->waited = true;
+      r->t_first = Clock::now();
     }
     in_step.push_back(r);
     while (r->next_block < r->blocks && n < s->step_blocks) {
@@ -292,7 +296,10 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
       d.t0 = tx0 | (ty0 << 16);
       d.sblk = (uint32_t)(r->tile_base / (size_t)(s->shape.gx * s->shape.gy) + b);
     }
-    if (r->next_block == r->blocks) finishing.push_back(r);
+    if (r->next_block == r->blocks) {
+      finishing.push_back(r);
+      r->t_last = Clock::now();
+    }
   }
   // the finishing requests' image entries for their ordering kernels
   // (blocks numbered from 0 within the request's slot range) follow the
@@ -359,11 +366,12 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
         f.n_imgs = (uint32_t)n_x;
         f.list = s->fine_list;
         f.count = s->fine_count;
-        f.gx = (uint32_t)s->shape.gx;
         f.level = (uint32_t)s->L;
         f.thr = s->params.mse_thr[s->L - 1];
         f.phase2 = a.phase2;
         f.identity_only = a.identity_only;
+        f.nt = (uint32_t)(s->shape.gx * s->shape.gy);
+        f.cells = (uint32_t)s->cells;
         f.staging = s->staging;
         f.masks = s->masks;
         const uint64_t bm4 = s->params.b_max / 4;
@@ -379,7 +387,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     e = fe::launch_scatter(dim + j, 1, nullptr, r->tiles, s->cells, s->shape, s->masks + r->tile_base,
                            reinterpret_cast<uint32_t*>(s->dev_base + r->csum_off),
                            reinterpret_cast<uint64_t*>(s->dev_base + r->cbase_off),
-                           s->staging + r->tile_base * (size_t)s->cells, reinterpret_cast<uint4*>(hout), r->cap,
+                           s->staging + r->tile_base * (size_t)(s->cells + 1), reinterpret_cast<uint4*>(hout), r->cap,
                            reinterpret_cast<uint64_t*>(hout + r->cap * 16), s->compute);
     if (e == hipSuccess) e = hipEventRecord(s->ev_done[r->slot], s->compute);
   }
@@ -485,14 +493,14 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   s->step_blocks = step_blocks;
   // a quarter of the budget holds tile slots (records + masks), the rest
   // images, outputs and ordering scratch
-  const size_t tile_bytes = (size_t)s->cells * 16 + 8;
+  const size_t tile_bytes = (size_t)(s->cells + 1) * 16 + 8;   // record slots and mask
   const size_t tiles_cap = (hbm_budget / 4) / tile_bytes;
   const size_t byte_budget = hbm_budget - tiles_cap * tile_bytes;
   (void)hipSetDevice(device);
   bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->dev_base), byte_budget) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * s->cells * 16) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&s->staging), tiles_cap * (s->cells + 1) * 16) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
@@ -684,6 +692,20 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
   return FE_OK;
 }
 
+fe_status fe_server_request_times(fe_server* s, uint64_t req, double* ms, uint32_t n) {
+  fe::clear_error();
+  if (!s || (n && !ms)) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(req);
+  if (it == s->all.end()) return fe::fail(FE_ERR_INVALID, "unknown request %llu", (unsigned long long)req);
+  const Request* r = it->second;
+  if (r->state != ReqState::Done) return fe::fail(FE_ERR_BUSY, "request %llu is not done", (unsigned long long)req);
+  const Clock::time_point t[4] = {r->t_admit, r->t_first, r->t_last, r->t_done};
+  for (uint32_t k = 0; k < n && k < 4; ++k)
+    ms[k] = std::chrono::duration<double, std::milli>(t[k] - r->t_submit).count();
+  return FE_OK;
+}
+
 fe_status fe_server_wait(fe_server* s, uint32_t timeout_us, uint64_t* req) {
   fe::clear_error();
   if (!s || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
@@ -703,7 +725,7 @@ fe_status fe_server_stats(fe_server* s, uint64_t* steps, uint64_t* blocks, uint6
   if (steps) *steps = s->steps;
   if (blocks) *blocks = s->blocks_run;
   if (completed) *completed = s->completed;
-  if (hbm_used) *hbm_used = s->dev_arena.used() + s->tile_arena.used() * ((size_t)s->cells * 16 + 8);
+  if (hbm_used) *hbm_used = s->dev_arena.used() + s->tile_arena.used() * ((size_t)(s->cells + 1) * 16 + 8);
   if (in_flight) *in_flight = (uint32_t)s->active.size();
   if (queued) *queued = (uint32_t)s->queued.size();
   return FE_OK;

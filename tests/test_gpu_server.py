@@ -182,3 +182,28 @@ def test_server_2x2_tree(torch_dev, ctx, budget, step_blocks):
         res = drain(srv, reqs)
     for k, im in enumerate(imgs):
         assert res[k][0].tobytes() == np.ascontiguousarray(mns.encode(im, 16, 2, thr)).tobytes(), k
+
+
+def test_request_stage_times(torch_dev, ctx):
+    """The stage times of a finished request are ordered (admitted, first
+    step, last step, complete), non-negative and end at its latency; an
+    unknown or unfinished id is refused."""
+    imgs = mixed_images(6, 31, 128, 768)
+    with fb.Server(16, 4, THR, hbm_budget=1 << 30, host_budget=256 << 20, max_slots=8, step_blocks=64) as srv:
+        reqs = [srv.submit(im) for im in imgs]
+        seen = 0
+        t0 = time.time()
+        while seen < len(reqs):
+            rid = srv.wait(2000)
+            assert time.time() - t0 < 60, "server did not finish"
+            if rid is None:
+                continue
+            adm, first, last, done = srv.request_times(rid)
+            assert 0.0 <= adm <= first <= last <= done
+            ok, recs, lat = srv.poll(rid)
+            assert ok and abs(lat - done) < 1e-6
+            k = reqs.index(rid)
+            assert recs.tobytes() == alone(torch_dev, ctx, imgs[k]).tobytes()
+            seen += 1
+        with pytest.raises(fb.FeError):
+            srv.request_times(reqs[0])          # fetched: unknown now
