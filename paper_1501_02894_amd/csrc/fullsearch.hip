@@ -168,6 +168,11 @@ struct FsCfg {
   static constexpr int KC = K / KCS;
   static constexpr int LROWS = kStripsPerBlock + B - 1;   // staged plane rows
   static constexpr int LP = 32 + B + 12;                  // staged row pitch (bytes), multiple of 4
+  // The staged rows are held four times, copy k shifted left by k bytes, so
+  // that every lane reads its window's words aligned.  Copies lie 8 mod 32
+  // dwords apart: lanes col = 4w + k of a half-wave then hit 32 distinct
+  // banks.
+  static constexpr int CW = ((LROWS * (LP / 4) + 23) / 32) * 32 + 8;   // dwords per copy
 };
 
 template <int B, int NF>
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
                                                      const double* qd, uint64_t* best, uint32_t xblocks,
                                                      uint32_t tblocks) {
   using C = FsCfg<B, NF>;
-  __shared__ uint32_t s_pl[C::LROWS * C::LP / 4 + 4];
+  __shared__ uint32_t s_pl[4 * C::CW];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 5, col = lane & 31;
   // domain block: parity class, block of plane rows, block of 32 columns
   uint32_t db = blockIdx.y;
@@ -189,19 +194,25 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
   const uint32_t t0 = tb * kStripsPerBlock, x0 = xb * 32u;
   if (t0 >= nrows || x0 >= ncols) return;
   const uint8_t* plane = g.planes + (size_t)cls * g.pitch * g.prow;
-  // stage plane rows t0 .. t0 + LROWS - 1, columns x0 .. x0 + LP - 1
-  for (int i = tid; i < C::LROWS * (C::LP / 4); i += 256) {
-    const int r = i / (C::LP / 4), c4 = i - r * (C::LP / 4);
+  // stage plane rows t0 .. t0 + LROWS - 1, columns x0 .. x0 + LP - 1, in
+  // four copies shifted by 0..3 bytes (the last words of a row read up to 3
+  // bytes past it, inside the plane's padded pitch, and are never used)
+  for (int i = tid; i < 4 * C::LROWS * (C::LP / 4); i += 256) {
+    const int k = i / (C::LROWS * (C::LP / 4));
+    const int i2 = i - k * (C::LROWS * (C::LP / 4));
+    const int r = i2 / (C::LP / 4), c4 = i2 - r * (C::LP / 4);
     uint32_t v = 0;
     const uint32_t row = t0 + (uint32_t)r;
     if (row < g.prow) {
-      const uint8_t* s = plane + (size_t)row * g.pitch + x0 + 4 * c4;
+      const uint8_t* s = plane + (size_t)row * g.pitch + x0 + 4 * c4 + k;
       v = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16) | ((uint32_t)s[3] << 24);
     }
     // staged centred: d - 128 == d ^ 0x80 as int8
-    s_pl[r * (C::LP / 4) + c4] = v ^ 0x80808080u;
+    s_pl[k * C::CW + r * (C::LP / 4) + c4] = v ^ 0x80808080u;
   }
   __syncthreads();
+  // this lane's copy and word column: every window row starts word-aligned
+  const uint32_t* s_col = s_pl + (col & 3) * C::CW + (col >> 2);
 
   // A fragments of this wave (registers)
   const uint32_t F0 = (blockIdx.x * 4u + (uint32_t)wave) * NF;
@@ -263,38 +274,23 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
       v4i bfr = {0, 0, 0, 0};
       if constexpr (B == 16) {
         const int row = t + 2 * c + grp;           // K q0 = 32c + 16 grp -> row q0 / 16
-        const int off = row * C::LP + col;
-        const int w0 = off >> 2;
-        const uint32_t sh = (uint32_t)off & 3u;
-        uint32_t x[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) x[k] = s_pl[w0 + k];
-        bfr.x = (int)__builtin_amdgcn_alignbyte(x[1], x[0], sh);
-        bfr.y = (int)__builtin_amdgcn_alignbyte(x[2], x[1], sh);
-        bfr.z = (int)__builtin_amdgcn_alignbyte(x[3], x[2], sh);
-        bfr.w = (int)__builtin_amdgcn_alignbyte(x[4], x[3], sh);
+        const uint32_t* w = s_col + row * (C::LP / 4);
+        bfr.x = (int)w[0];
+        bfr.y = (int)w[1];
+        bfr.z = (int)w[2];
+        bfr.w = (int)w[3];
       } else if constexpr (B == 8) {
         const int row = t + 4 * c + 2 * grp;       // q0 = 32c + 16 grp -> rows q0 / 8, +1
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int off = (row + h) * C::LP + col;
-          const int w0 = off >> 2;
-          const uint32_t sh = (uint32_t)off & 3u;
-          const uint32_t x0w = s_pl[w0], x1w = s_pl[w0 + 1], x2w = s_pl[w0 + 2];
-          const int lo = (int)__builtin_amdgcn_alignbyte(x1w, x0w, sh);
-          const int hi = (int)__builtin_amdgcn_alignbyte(x2w, x1w, sh);
-          if (h == 0) { bfr.x = lo; bfr.y = hi; } else { bfr.z = lo; bfr.w = hi; }
-        }
+        const uint32_t* w = s_col + row * (C::LP / 4);
+        bfr.x = (int)w[0];
+        bfr.y = (int)w[1];
+        bfr.z = (int)w[C::LP / 4];
+        bfr.w = (int)w[C::LP / 4 + 1];
       } else {
         const int row = t + 2 * grp;               // q0 = 8 grp -> rows 2 grp, +1
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int off = (row + h) * C::LP + col;
-          const int w0 = off >> 2;
-          const uint32_t sh = (uint32_t)off & 3u;
-          const int val = (int)__builtin_amdgcn_alignbyte(s_pl[w0 + 1], s_pl[w0], sh);
-          if (h == 0) bfr.x = val; else bfr.y = val;
-        }
+        const uint32_t* w = s_col + row * (C::LP / 4);
+        bfr.x = (int)w[0];
+        bfr.y = (int)w[C::LP / 4];
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
