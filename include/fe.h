@@ -441,7 +441,9 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
                       uint32_t* gy, double* ms, void* stream);
 
 /*
- * Encode server (continuous batching).  One parameter set per server.
+ * Encode server (continuous batching).  The server's parameter set fixes
+ * the block sizes (b_max, b_min: the kernel it runs); each request may bring
+ * its own thresholds and FE_PHASE2 / FE_IDENTITY_ONLY flags.
  *
  * fe_server_create: device memory of `hbm_budget` bytes (a quarter holds
  * per-tile record slots and masks, the rest images and ordering scratch)
@@ -455,6 +457,10 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  *
  * fe_server_submit copies the host image (W x H, row pitch `stride`) into
  * pinned staging and queues it; the caller may reuse h_img on return.
+ * `params` (copied; NULL = the server's) are the request's encoder
+ * parameters: b_max and b_min must equal the server's and flags may hold
+ * FE_PHASE2 and FE_IDENTITY_ONLY only (FE_ERR_INVALID otherwise); requests
+ * with different parameters share steps.
  * FE_ERR_BUSY when the pinned staging is full (retry later), FE_ERR_OOM
  * when the request can never fit the device budget, FE_ERR_SHAPE /
  * FE_ERR_INVALID as fe_validate.  Requests are admitted in arrival order
@@ -471,7 +477,8 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  * *n, else FE_ERR_CAPACITY and nothing is released) and the request is
  * released (its id becomes unknown).  A request that failed on the device
  * returns FE_ERR_DEVICE and is released.  The stream equals fe_encode's for
- * the same image and parameters, whatever else was in flight.
+ * the same image and the request's parameters, whatever else (and with
+ * whatever parameters) was in flight.
  *
  * fe_server_wait blocks up to `timeout_us` microseconds for a request to
  * finish (done or failed) and returns its id, each finished id once, in
@@ -487,9 +494,9 @@ typedef struct fe_server fe_server;
 fe_status fe_server_create(int device, const fe_params* params, size_t hbm_budget, size_t host_budget,
                            uint32_t max_slots, uint32_t step_blocks, fe_server** out);
 fe_status fe_server_submit(fe_server* server, const uint8_t* h_img, uint32_t width, uint32_t height,
-                           uint32_t stride, uint64_t* req);
+                           uint32_t stride, const fe_params* params, uint64_t* req);
 fe_status fe_server_submit_pinned(fe_server* server, const uint8_t* h_img, uint32_t width, uint32_t height,
-                                  uint32_t stride, uint64_t* req);
+                                  uint32_t stride, const fe_params* params, uint64_t* req);
 fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, size_t cap, size_t* n,
                          int* done, double* latency_ms);
 fe_status fe_server_wait(fe_server* server, uint32_t timeout_us, uint64_t* req);

@@ -111,8 +111,10 @@ _SIGNATURES = {
     "fe_full_search_ranges": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _VP, _U32, _VP, _VP]),
     "fe_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(fe_params), _SZ, _SZ, _U32, _U32,
                                         ctypes.POINTER(_VP)]),
-    "fe_server_submit": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_uint64)]),
-    "fe_server_submit_pinned": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_submit": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params),
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_submit_pinned": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params),
+                                               ctypes.POINTER(ctypes.c_uint64)]),
     "fe_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _SZ, ctypes.POINTER(_SZ), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_double)]),
     "fe_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
@@ -481,20 +483,24 @@ def fe_server_create(device: int, params: fe_params, hbm_budget: int, host_budge
     return h.value
 
 
-def fe_server_submit(server: int, img: np.ndarray) -> int:
+def fe_server_submit(server: int, img: np.ndarray, params: fe_params = None) -> int:
+    """Queue a host image; `params` (None: the server's) may change the
+    thresholds and the phase-2 / identity-only flags, not the block sizes."""
     img = np.ascontiguousarray(img, dtype=np.uint8)
     H, W = img.shape
     req = ctypes.c_uint64(0)
-    _check(load().fe_server_submit(server, img.ctypes.data, W, H, W, ctypes.byref(req)))
+    _check(load().fe_server_submit(server, img.ctypes.data, W, H, W,
+                                   ctypes.byref(params) if params is not None else None, ctypes.byref(req)))
     return req.value
 
 
-def fe_server_submit_pinned(server: int, img) -> int:
+def fe_server_submit_pinned(server: int, img, params: fe_params = None) -> int:
     """Submit a 2-D uint8 torch tensor in pinned host memory (no host copy;
     keep it unchanged until the request is done)."""
     H, W = img.shape
     req = ctypes.c_uint64(0)
-    _check(load().fe_server_submit_pinned(server, int(img.data_ptr()), W, H, img.stride(0), ctypes.byref(req)))
+    _check(load().fe_server_submit_pinned(server, int(img.data_ptr()), W, H, img.stride(0),
+                                          ctypes.byref(params) if params is not None else None, ctypes.byref(req)))
     return req.value
 
 
@@ -548,18 +554,19 @@ def fe_server_destroy(server: int) -> None:
 
 
 class Server:
-    """Continuous-batching encode server (one parameter set)."""
+    """Continuous-batching encode server: block sizes fixed at creation,
+    thresholds and flags per request (default: the creation's)."""
 
     def __init__(self, b_max, b_min, thresholds, phase2=True, device=0, hbm_budget=8 << 30,
                  host_budget=2 << 30, max_slots=256, step_blocks=4096):
         self.handle = fe_server_create(device, make_params(b_max, b_min, thresholds, phase2), hbm_budget,
                                        host_budget, max_slots, step_blocks)
 
-    def submit(self, img):
-        return fe_server_submit(self.handle, img)
+    def submit(self, img, params=None):
+        return fe_server_submit(self.handle, img, params)
 
-    def submit_pinned(self, img):
-        return fe_server_submit_pinned(self.handle, img)
+    def submit_pinned(self, img, params=None):
+        return fe_server_submit_pinned(self.handle, img, params)
 
     def poll(self, req, fetch=True):
         return fe_server_poll(self.handle, req, fetch)

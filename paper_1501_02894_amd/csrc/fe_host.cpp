@@ -276,7 +276,6 @@ fe_status build_table(const fe_image_desc* imgs, uint32_t n_imgs, const fe_param
     d.groups_x = (d.tiles_x + shape.gx - 1) / shape.gx;
     d.groups_y = (d.tiles_y + shape.gy - 1) / shape.gy;
     d.wg_first = wgs;
-    d.pad = 0;
     d.tile_first = tiles;
     const uint64_t g = (uint64_t)d.groups_x * d.groups_y;
     if (wgs + g > 0x7fffffffull) return fe::fail(FE_ERR_SHAPE, "batch too large (workgroups)");

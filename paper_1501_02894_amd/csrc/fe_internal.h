@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "fe.h"
+
 namespace fe {
 
 // One image as the device sees it (batch table entry).
@@ -14,9 +16,18 @@ struct ImgDev {
   uint32_t tiles_x, tiles_y;    // top-level tiles per row / column
   uint32_t groups_x, groups_y;  // workgroup super-tiles per row / column
   uint32_t wg_first;            // first logical workgroup of this image
-  uint32_t pad;
+  // the 2 x 2 level's parameters for this image, read when
+  // FinishArgs::per_image is set: FE_PHASE2 / FE_IDENTITY_ONLY flags and
+  // the MSE threshold of the listed 4 x 4 ranges
+  uint32_t fine_flags;
+  uint32_t fine_thr;
   uint64_t tile_first;          // global index of this image's first tile
 };
+static_assert(sizeof(ImgDev) == 56, "image table entry");
+
+// Per-workgroup encoder parameters (EncodeArgs::wg_params): the MSE
+// thresholds of levels 1..L-1, then FE_PHASE2 / FE_IDENTITY_ONLY flags.
+constexpr int kWgParamWords = 8;
 
 // One workgroup's block of top tiles, expanded from the image table by the
 // prep kernel so that a workgroup starts with a single 32-byte load.
@@ -39,6 +50,10 @@ struct EncodeArgs {
   uint32_t phase2;     // run Technique 1
   uint32_t identity_only;   // phase 1 fits the identity isometry only
   uint32_t thr[4];     // MSE thresholds of levels 1..L-1
+  // when not NULL, kWgParamWords words per logical workgroup that replace
+  // thr, phase2 and identity_only for that workgroup (callers that mix
+  // parameter sets in one launch)
+  const uint32_t* wg_params;
   // Record slots, one group of NT * cells per workgroup block (NT tiles),
   // cell-major inside it: the record of Morton cell c of the block's tile t
   // is at sblk * NT * cells + c * NT + t, so the one-record tiles of a block
@@ -119,6 +134,7 @@ struct FinishArgs {
   uint32_t level;       // 1-based level of the listed 4 x 4 ranges
   uint32_t thr;         // their MSE threshold (phase 2)
   uint32_t phase2, identity_only;
+  uint32_t per_image;   // take thr / phase2 / identity_only from each range's image entry
   // record slots per block: nt whole-tile slots, then cells per tile (a
   // listed range that is a whole tile stores its phase-2 record in the former)
   uint32_t nt, cells;

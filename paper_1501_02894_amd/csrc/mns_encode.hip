@@ -84,6 +84,36 @@ struct BlockGeo {
   uint32_t sblk;         // record-slot block
 };
 
+// A workgroup's thresholds and flags (workgroup-uniform): the call's, or
+// its own words when the call mixes parameter sets.  Selected by value, not
+// indexed, so that they stay in scalar registers.
+struct LevelParams {
+  uint32_t t0, t1, t2, t3;
+  bool phase2, identity_only;
+  __device__ __forceinline__ uint32_t thr(int l) const { return l == 0 ? t0 : l == 1 ? t1 : l == 2 ? t2 : t3; }
+};
+
+__device__ __forceinline__ LevelParams level_params(const EncodeArgs& a, uint32_t wg) {
+  LevelParams p;
+  if (a.wg_params) {
+    const uint32_t* w = a.wg_params + (size_t)wg * kWgParamWords;
+    p.t0 = w[0];
+    p.t1 = w[1];
+    p.t2 = w[2];
+    p.t3 = w[3];
+    p.phase2 = (w[4] & FE_PHASE2) != 0;
+    p.identity_only = (w[4] & FE_IDENTITY_ONLY) != 0;
+  } else {
+    p.t0 = a.thr[0];
+    p.t1 = a.thr[1];
+    p.t2 = a.thr[2];
+    p.t3 = a.thr[3];
+    p.phase2 = a.phase2 != 0;
+    p.identity_only = a.identity_only != 0;
+  }
+  return p;
+}
+
 template <int BMAX, int GX, int GY>
 __device__ __forceinline__ BlockGeo block_geo(const BlockDesc& d) {
   BlockGeo b;
@@ -334,8 +364,8 @@ __device__ __forceinline__ uint32_t rec_slot(int tx, int ty, int cell, bool whol
 // per wave) into the parent list of the next level.  A barrier ends each
 // level.
 template <int BMAX, int L, int GX, int GY, bool EXT>
-__device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm,
-                                              uint32_t rot) {
+__device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelParams& P, const BlockGeo& bg,
+                                              Lds<BMAX, L, GX, GY>& sm, uint32_t rot) {
   using G = Geo<BMAX, L, GX, GY>;
   // record cells per tile: B_min cells, or 2 x 2 cells when the tree goes on
   // to 2 x 2 (EXT), whose Morton codes are those of the B_min cells times 4
@@ -369,13 +399,13 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
       constexpr double NN = (double)(BB * BB);
       using W = Window<G, BB>;
       // 64 n^2 t of this level; a forced level accepts every range
-      const double thr64 = last ? __builtin_inf() : 64.0 * NN * NN * (double)a.thr[lev - 1];
+      const double thr64 = last ? __builtin_inf() : 64.0 * NN * NN * (double)P.thr(lev - 1);
 
       // Fit, Technique 1, records and compaction for list entry e, lane =
       // e mod 64, given the range's moments in acc.
       auto finish = [&](int e, bool valid, uint32_t (&acc)[12]) {
         const RangeRef r = range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1));
-        if (a.identity_only) {   // every isometry scores as the identity: the fit keeps e = 0
+        if (P.identity_only) {   // every isometry scores as the identity: the fit keeps e = 0
 #pragma unroll
           for (int j = 5; j < 12; ++j) acc[j] = acc[4];
         }
@@ -385,11 +415,11 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const BlockGe
         // ---- Technique 1 for the parent of this quad of children
         bool dead = false;   // the parent was stored by phase 2
         if constexpr (BB < BMAX) {
-          if (a.phase2) {
+          if (P.phase2) {
             constexpr int LOGNB = 2 * Log2<BB>::value;
             int c1, c2, delta;
             phase2_consts(lev - 1, c1, c2, delta);
-            const double thr2 = 400.0 * NN * NN * (double)a.thr[lev - 2];
+            const double thr2 = 400.0 * NN * NN * (double)P.thr(lev - 2);
             const int c = e & 3;
             const int m = r.m;
             int O = (int)((2u * acc[0] + (uint32_t)(BB * BB)) >> (LOGNB + 1));
@@ -585,8 +615,9 @@ __global__ __launch_bounds__(256) void mns_tiles_kernel(EncodeArgs a) {
   st.load(bg, tid);
   st.store(bg, tid, sm.img, sm.h0, sm.h0t);
   block_start(bg, sm, tid);
+  const LevelParams P = level_params(a, wg);
   __syncthreads();
-  process_block<BMAX, L, GX, GY, EXT>(a, bg, sm, wg & 3u);
+  process_block<BMAX, L, GX, GY, EXT>(a, P, bg, sm, wg & 3u);
 }
 
 // One lane per logical workgroup: find its image (binary search over the

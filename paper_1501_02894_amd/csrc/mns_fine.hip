@@ -41,6 +41,8 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
       if (a.imgs[mid].tile_first <= tile) lo = mid; else hi = mid - 1;
     }
     const ImgDev im = a.imgs[lo];
+    const uint32_t flags = a.per_image ? im.fine_flags : (a.phase2 ? FE_PHASE2 : 0u) | (a.identity_only ? FE_IDENTITY_ONLY : 0u);
+    const uint32_t thr = a.per_image ? im.fine_thr : a.thr;
     const int W = (int)im.width, H = (int)im.height;
     const int px = (int)(ent.x & 0xffffu), py = (int)(ent.x >> 16);
     const int cx = px + 2 * (c & 1), cy = py + 2 * (c >> 1);
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
         acc[11] += v * d[j2][i2];  // T_7: d[1-j][1-i]
       }
     }
-    if (a.identity_only) {
+    if (flags & FE_IDENTITY_ONLY) {
 #pragma unroll
       for (int j = 5; j < 12; ++j) acc[j] = acc[4];
     }
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
     bool dead = false;
     int O[4] = {0, 0, 0, 0};
     uint32_t bits = 0;
-    if (a.phase2) {
+    if (flags & FE_PHASE2) {
       uint32_t mom[4][5];
       const int g0 = (int)(threadIdx.x & 63u) & ~3;
 #pragma unroll
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void fine_finish_kernel(FinishArgs a) {
 #pragma unroll
         for (int j = 0; j < 5; ++j) mom[k][j] = (uint32_t)__shfl((int)acc[j], g0 + k);
       }
-      dead = fit_phase2<2>(mom, m, (int)a.level, a.thr, O, bits);
+      dead = fit_phase2<2>(mom, m, (int)a.level, thr, O, bits);
     }
     if (dead) {
       // a listed range that is a whole top tile (trees 4 -> 2) keeps its

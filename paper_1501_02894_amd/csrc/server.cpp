@@ -1,6 +1,7 @@
 // Continuous-batching encode server.
 //
-// Requests (host images, one parameter set per server) are queued by
+// Requests (host images, each with its own thresholds and Technique-1 /
+// identity-only flags over the server's block sizes) are queued by
 // fe_server_submit.  A worker thread runs steps:
 //   1. admission: queued requests enter in arrival order while a slot is
 //      free and their device footprint fits: image, output, per-request
@@ -10,7 +11,9 @@
 //   2. one launch of the fused MNS kernel over up to `step_blocks` blocks of
 //      top tiles taken first-come first-served from every admitted request
 //      whose image has arrived: mixed image sizes share the launch, and a
-//      large image is spread over several steps;
+//      large image is spread over several steps; each block carries its
+//      request's parameter set, so requests with different thresholds share
+//      the launch too;
 //   3. a request whose last block has run gets its stream ordered by a
 //      kernel that writes the records and their count straight into the
 //      request's pinned host buffer; the request completes when that
@@ -97,6 +100,8 @@ struct Request {
   uint32_t w = 0, h = 0, pitch = 0;
   uint32_t tiles_x = 0, tiles_y = 0, groups_x = 0;
   uint64_t tiles = 0, blocks = 0, next_block = 0;
+  uint32_t thr[4] = {0, 0, 0, 0};        // MSE thresholds of levels 1..L-1
+  uint32_t flags = 0;                    // FE_PHASE2 / FE_IDENTITY_ONLY
   size_t cap = 0;                        // device output capacity (transforms)
   size_t chunks = 0;
   size_t hin_off = 0, hin_len = 0;       // pinned host input copy
@@ -137,6 +142,7 @@ struct fe_server {
   uint32_t max_slots = 0, step_blocks = 0;
   fe::BlockDesc* h_desc[2] = {nullptr, nullptr};
   fe::BlockDesc* d_desc[2] = {nullptr, nullptr};
+  std::vector<uint32_t> wg_words;        // a step's per-block parameter words (worker thread)
   hipEvent_t step_done[2] = {nullptr, nullptr};
   int step_slot = 0;
   std::vector<hipEvent_t> ev_copied, ev_done;   // per admission slot
@@ -164,6 +170,12 @@ size_t byte_footprint(const Request* r) {
 }
 
 size_t host_out_bytes(const Request* r) { return r->cap * 16 + 16; }
+
+// Bytes of a step's upload: `blocks` block descriptors, their parameter
+// words, then `imgs` image entries.
+size_t desc_bytes(uint32_t blocks, size_t imgs) {
+  return (size_t)blocks * (sizeof(fe::BlockDesc) + fe::kWgParamWords * sizeof(uint32_t)) + imgs * sizeof(fe::ImgDev);
+}
 
 // Tile slots of a request: its workgroup blocks, each a full GX x GY group
 // (record slots are laid out per block).
@@ -276,6 +288,10 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   fe::BlockDesc* hd = s->h_desc[slot];
   uint32_t n = 0;
   std::vector<Request*> finishing, first_time, in_step;
+  // per-block parameter words, written beside the descriptors and moved
+  // behind the last one before the upload
+  std::vector<uint32_t>& hp = s->wg_words;
+  hp.resize((size_t)s->step_blocks * fe::kWgParamWords);
   for (Request* r : ready) {
     if (n >= s->step_blocks) break;
     if (!r->waited) {
@@ -295,16 +311,21 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
       d.wh = (r->w - 1u) | ((r->h - 1u) << 16);
       d.t0 = tx0 | (ty0 << 16);
       d.sblk = (uint32_t)(r->tile_base / (size_t)(s->shape.gx * s->shape.gy) + b);
+      uint32_t* w = hp.data() + (size_t)(n - 1) * fe::kWgParamWords;
+      for (int l = 0; l < 4; ++l) w[l] = r->thr[l];
+      w[4] = r->flags;
+      w[5] = w[6] = w[7] = 0u;
     }
     if (r->next_block == r->blocks) {
       finishing.push_back(r);
       r->t_last = Clock::now();
     }
   }
-  // the finishing requests' image entries for their ordering kernels
-  // (blocks numbered from 0 within the request's slot range) follow the
-  // block descriptors in the same upload
-  fe::ImgDev* him = reinterpret_cast<fe::ImgDev*>(hd + n);
+  // one upload: the n descriptors, their parameter words, then the
+  // finishing requests' image entries for their ordering kernels (blocks
+  // numbered from 0 within the request's slot range)
+  memcpy(hd + n, hp.data(), (size_t)n * fe::kWgParamWords * sizeof(uint32_t));
+  fe::ImgDev* him = reinterpret_cast<fe::ImgDev*>(reinterpret_cast<uint32_t*>(hd + n) + (size_t)n * fe::kWgParamWords);
   for (size_t j = 0; j < finishing.size(); ++j) {
     const Request* r = finishing[j];
     fe::ImgDev& im = him[j];
@@ -331,12 +352,15 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
       im.width = r->w;
       im.height = r->h;
       im.stride = r->pitch;
+      im.fine_flags = r->flags;
+      im.fine_thr = r->thr[s->L - 1];
       im.tile_first = r->tile_base;
     }
   }
   const size_t n_x = s->ext ? in_step.size() : 0;
-  const size_t upload = (size_t)n * sizeof(fe::BlockDesc) + (finishing.size() + n_x) * sizeof(fe::ImgDev);
-  const fe::ImgDev* dim = reinterpret_cast<const fe::ImgDev*>(s->d_desc[slot] + n);
+  const size_t upload = desc_bytes(n, finishing.size() + n_x);
+  const uint32_t* dparams = reinterpret_cast<const uint32_t*>(s->d_desc[slot] + n);
+  const fe::ImgDev* dim = reinterpret_cast<const fe::ImgDev*>(dparams + (size_t)n * fe::kWgParamWords);
   const fe::ImgDev* dx_tab = dim + finishing.size();
   lk.unlock();
   hipError_t e = hipSuccess;
@@ -348,9 +372,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
     a.blocks = s->d_desc[slot];
     a.n_imgs = 1;
     a.n_wg = n;
-    a.phase2 = (s->params.flags & FE_PHASE2) ? 1u : 0u;
-    a.identity_only = (s->params.flags & FE_IDENTITY_ONLY) ? 1u : 0u;
-    for (int l = 0; l < 4; ++l) a.thr[l] = l < (int)s->params.n_thr ? s->params.mse_thr[l] : 0u;
+    a.wg_params = dparams;
     a.staging = s->staging;
     a.masks = s->masks;
     if (!s->ext) {
@@ -367,9 +389,7 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
         f.list = s->fine_list;
         f.count = s->fine_count;
         f.level = (uint32_t)s->L;
-        f.thr = s->params.mse_thr[s->L - 1];
-        f.phase2 = a.phase2;
-        f.identity_only = a.identity_only;
+        f.per_image = 1;
         f.nt = (uint32_t)(s->shape.gx * s->shape.gy);
         f.cells = (uint32_t)s->cells;
         f.staging = s->staging;
@@ -504,13 +524,11 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
             hipMalloc(reinterpret_cast<void**>(&s->masks), tiles_cap * 8) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&s->host_base), host_budget, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
-    // per step: the block descriptors, then one image entry per finishing
-    // request and (ext) one per request of the step
-    ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]),
-                       (size_t)step_blocks * (sizeof(fe::BlockDesc) + 2 * sizeof(fe::ImgDev)),
+    // per step: the block descriptors and their parameter words, then one
+    // image entry per finishing request and (ext) one per request of the step
+    ok = hipHostMalloc(reinterpret_cast<void**>(&s->h_desc[k]), desc_bytes(step_blocks, 2 * (size_t)step_blocks),
                        hipHostMallocDefault) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]),
-                   (size_t)step_blocks * (sizeof(fe::BlockDesc) + 2 * sizeof(fe::ImgDev))) ==
+         hipMalloc(reinterpret_cast<void**>(&s->d_desc[k]), desc_bytes(step_blocks, 2 * (size_t)step_blocks)) ==
              hipSuccess &&
          hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
   if (ok && s->ext) {
@@ -575,11 +593,23 @@ void fe_server_destroy(fe_server* s) {
 
 namespace {
 
-// A new request for a W x H image (not yet queued), or NULL with the error set.
-Request* new_request(fe_server* s, uint32_t w, uint32_t h, uint32_t stride, fe_status& st) {
+// A new request for a W x H image (not yet queued), or NULL with the error
+// set.  p: its parameters (NULL: the server's), which may differ from the
+// server's in their thresholds and FE_PHASE2 / FE_IDENTITY_ONLY flags only.
+Request* new_request(fe_server* s, uint32_t w, uint32_t h, uint32_t stride, const fe_params* p, fe_status& st) {
+  if (!p) p = &s->params;
+  st = fe::check_params(p);
+  if (st != FE_OK) return nullptr;
+  if (p->b_max != s->params.b_max || p->b_min != s->params.b_min ||
+      (p->flags & ~(uint32_t)(FE_PHASE2 | FE_IDENTITY_ONLY)) != 0) {
+    st = fe::fail(FE_ERR_INVALID, "request parameters must keep the server's b_max / b_min and run MNS or no-search");
+    return nullptr;
+  }
   st = fe::check_shape(w, h, stride, s->params.b_max);
   if (st != FE_OK) return nullptr;
   Request* r = new Request();
+  for (int l = 0; l < 4; ++l) r->thr[l] = l < (int)p->n_thr ? p->mse_thr[l] : 0u;
+  r->flags = p->flags;
   r->w = w;
   r->h = h;
   r->pitch = w;   // W is a multiple of b_max >= 4
@@ -612,11 +642,11 @@ void enqueue(fe_server* s, Request* r, uint64_t* req) {
 }  // namespace
 
 fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
-                           uint64_t* req) {
+                           const fe_params* params, uint64_t* req) {
   fe::clear_error();
   if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
   fe_status st;
-  Request* r = new_request(s, w, h, stride, st);
+  Request* r = new_request(s, w, h, stride, params, st);
   if (!r) return st;
   std::unique_lock<std::mutex> lk(s->mu);
   const size_t hin = s->host_arena.alloc((size_t)r->pitch * h);
@@ -640,7 +670,7 @@ fe_status fe_server_submit(fe_server* s, const uint8_t* h_img, uint32_t w, uint3
 }
 
 fe_status fe_server_submit_pinned(fe_server* s, const uint8_t* h_img, uint32_t w, uint32_t h, uint32_t stride,
-                                  uint64_t* req) {
+                                  const fe_params* params, uint64_t* req) {
   fe::clear_error();
   if (!s || !h_img || !req) return fe::fail(FE_ERR_INVALID, "NULL argument");
   hipPointerAttribute_t attr{};
@@ -649,7 +679,7 @@ fe_status fe_server_submit_pinned(fe_server* s, const uint8_t* h_img, uint32_t w
     return fe::fail(FE_ERR_INVALID, "image is not in pinned host memory");
   }
   fe_status st;
-  Request* r = new_request(s, w, h, stride, st);
+  Request* r = new_request(s, w, h, stride, params, st);
   if (!r) return st;
   r->hsrc = h_img;
   r->hstride = stride;

@@ -207,3 +207,47 @@ def test_request_stage_times(torch_dev, ctx):
             seen += 1
         with pytest.raises(fb.FeError):
             srv.request_times(reqs[0])          # fetched: unknown now
+
+
+# parameter sets that share one server: thresholds, Technique 1 on / off,
+# identity-only fits
+MIXED_SETS = [
+    dict(thresholds=[300, 200], phase2=True, identity_only=False),
+    dict(thresholds=[40, 900], phase2=True, identity_only=False),
+    dict(thresholds=[300, 200], phase2=False, identity_only=False),
+    dict(thresholds=[120, 60], phase2=True, identity_only=True),
+]
+
+
+@pytest.mark.parametrize("b_min,extra", [(4, []), (2, [50])])
+def test_server_per_request_params(torch_dev, ctx, b_min, extra):
+    """Requests with different thresholds and flags share steps; each
+    stream equals the image encoded alone with its own parameters (and the
+    oracle for the small ones).  Block sizes other than the server's are
+    refused."""
+    imgs = mixed_images(16, 41, 64, 512)
+    sets = [dict(s, thresholds=s["thresholds"] + extra) for s in MIXED_SETS]
+    log(f"server 16 -> {b_min}, {len(sets)} parameter sets over {len(imgs)} images")
+    with fb.Server(16, b_min, sets[0]["thresholds"], max_slots=16, step_blocks=32) as srv:
+        reqs = []
+        for k, im in enumerate(imgs):
+            s = sets[k % len(sets)]
+            reqs.append(srv.submit(im, fb.make_params(16, b_min, s["thresholds"], s["phase2"],
+                                                      identity_only=s["identity_only"])))
+        res = drain(srv, reqs)
+        st = srv.stats()
+        with pytest.raises(fb.FeError) as ei:
+            srv.submit(imgs[0], fb.make_params(8, b_min, [100] * (len(extra) + 1)))
+        assert ei.value.status == fb.FE_ERR_INVALID
+        with pytest.raises(fb.FeError) as ei:
+            srv.submit(imgs[0], fb.make_params(16, b_min, sets[0]["thresholds"], full_search=True))
+        assert ei.value.status == fb.FE_ERR_INVALID
+    assert st["steps"] < len(imgs)          # requests shared steps
+    for k, im in enumerate(imgs):
+        s = sets[k % len(sets)]
+        want = fb.to_records(ctx.encode(torch_dev.from_numpy(im).cuda(), 16, b_min, s["thresholds"], s["phase2"],
+                                        identity_only=s["identity_only"]))
+        assert res[k][0].tobytes() == want.tobytes(), f"image {k} (set {k % len(sets)}) differs in the mix"
+        if im.size <= 128 * 128:
+            o = mns.encode(im, 16, b_min, s["thresholds"], phase2=s["phase2"], isometries=not s["identity_only"])
+            assert res[k][0].tobytes() == np.ascontiguousarray(o).tobytes(), k
