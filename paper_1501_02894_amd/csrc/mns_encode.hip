@@ -661,8 +661,8 @@ static hipError_t launch_one(const EncodeArgs& a, hipStream_t s) {
   X(4, 1, 16, 16) X(4, 1, 32, 8)                                                        \
   X(8, 1, 16, 8) X(8, 1, 8, 8) X(8, 2, 8, 8) X(8, 2, 16, 4) X(8, 2, 4, 4) X(8, 2, 8, 4)  \
   X(16, 1, 8, 4) X(16, 1, 4, 4) X(16, 2, 8, 4) X(16, 2, 4, 4) X(16, 2, 8, 2)             \
-  X(16, 3, 8, 8) X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2) X(16, 3, 8, 2)            \
-  X(16, 3, 4, 2) X(16, 3, 16, 4)                                                        \
+  X(16, 3, 8, 7) X(16, 3, 8, 8) X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2)            \
+  X(16, 3, 8, 2) X(16, 3, 4, 2) X(16, 3, 16, 4) X(16, 3, 8, 6)                          \
   X(32, 1, 4, 2) X(32, 1, 2, 2) X(32, 2, 4, 2) X(32, 2, 2, 2) X(32, 3, 4, 2)             \
   X(32, 3, 2, 2) X(32, 4, 4, 4) X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1) X(32, 4, 4, 1)
 
@@ -686,7 +686,7 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
 hipError_t launch_mns_tiles_ext(int b_max, int levels, TileShape shape, const EncodeArgs& a, hipStream_t s) {
   // the default shapes of 16 -> 4, 8 -> 4 and 4 -> 4, and the smallest of
   // the first two (for calls with few tiles)
-  if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 8) return launch_one<16, 3, 8, 8, true>(a, s);
+  if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 7) return launch_one<16, 3, 8, 7, true>(a, s);
   if (b_max == 16 && levels == 3 && shape.gx == 4 && shape.gy == 2) return launch_one<16, 3, 4, 2, true>(a, s);
   if (b_max == 8 && levels == 2 && shape.gx == 8 && shape.gy == 8) return launch_one<8, 2, 8, 8, true>(a, s);
   if (b_max == 8 && levels == 2 && shape.gx == 4 && shape.gy == 4) return launch_one<8, 2, 4, 4, true>(a, s);

@@ -81,23 +81,25 @@ constexpr unsigned kScatterGroups = 16384;
 // Records copied per pass of a chunk.
 constexpr int kPass = 1024;
 
-// Per-lane share (of 256 lanes) of the record counts in p[0, n): 8 loads
+// Per-lane share (of 256 lanes) of the record counts in p[0, n): U loads
 // in flight per round, addresses clamped, so that no load waits for the one
-// before it.
-__device__ __forceinline__ uint64_t count_of(uint32_t v) { return v; }
-__device__ __forceinline__ uint64_t count_of(uint64_t mask) { return (uint64_t)__popcll(mask); }
-template <typename T>
-__device__ __forceinline__ unsigned long long lane_sum(const T* p, uint64_t n, int tid) {
-  unsigned long long acc = 0;
-  for (uint64_t i0 = 0; i0 < n; i0 += 256u * 8u) {
-    T x[8];
+// before it.  A lane's share (and a wave's) stays below 2^32: at most
+// n / 256 entries (n <= kSumChunks chunk counts of at most 256 * 64 records
+// each, or at most 64 * 256 masks of at most 64 records each).
+__device__ __forceinline__ uint32_t count_of(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t count_of(uint64_t mask) { return (uint32_t)__popcll(mask); }
+template <int U, typename T>
+__device__ __forceinline__ uint32_t lane_sum(const T* p, uint64_t n, int tid) {
+  uint32_t acc = 0;
+  for (uint64_t i0 = 0; i0 < n; i0 += 256u * U) {
+    T x[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const uint64_t i = i0 + (uint64_t)tid + 256u * (uint64_t)u;
       x[u] = p[i < n ? i : n - 1u];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += i0 + (uint64_t)tid + 256u * (uint64_t)u < n ? count_of(x[u]) : 0u;
+    for (int u = 0; u < U; ++u) acc += i0 + (uint64_t)tid + 256u * (uint64_t)u < n ? count_of(x[u]) : 0u;
   }
   return acc;
 }
@@ -110,6 +112,15 @@ __device__ __forceinline__ unsigned long long lane_sum(const T* p, uint64_t n, i
 // records, each tile lane lists the slots of its records that fall in the
 // pass (lowest cell first), and the workgroup copies the pass with one
 // record per lane (coalesced writes).
+//
+// PREFIX says where the records before a chunk come from (the variants have
+// no branches around their first loads, which would make the compiler wait
+// for each load before the next): kPrefixMasks counts them from the masks
+// (few chunks), kPrefixSums adds up the per-chunk counts, kPrefixBase reads
+// them from the scan of those counts.  MULTI: several images (chunk_img
+// gives each chunk's first one); otherwise one image, entry 0.
+constexpr int kPrefixMasks = 0, kPrefixSums = 1, kPrefixBase = 2;
+template <int PREFIX, bool MULTI>
 __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32_t n_imgs,
                                                      const uint32_t* chunk_img, uint64_t total_tiles,
                                                      uint32_t n_chunks, int cells, int gx, int gy,
@@ -122,31 +133,46 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
   __shared__ unsigned long long s_rslot[kPass];
   __shared__ unsigned long long s_tf[kChunkImgs];      // the chunk's images: first tile,
   __shared__ uint32_t s_tx[kChunkImgs], s_gx[kChunkImgs], s_wf[kChunkImgs];   // tiles / blocks per row, first block
-  __shared__ unsigned long long s_red[4];
+  __shared__ uint32_t s_red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // a workgroup orders chunk blockIdx.x, then every gridDim.x-th chunk after
   // it (fewer, longer-lived workgroups: short ones are bound by their launch)
   for (uint32_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
   const uint64_t c0 = (uint64_t)chunk * kChunkTiles;
-  // independent loads first: this lane's tile mask and image entry
+  // the loads that depend on nothing are issued first (the chunk's first
+  // image, the counts before the chunk, this lane's tile mask), so that the
+  // image entries, which wait for the first, are the only second round trip
+  uint32_t k0 = 0;
+  if constexpr (MULTI) k0 = chunk_img[chunk];
   const uint64_t tile = c0 + (uint64_t)tid;
   const bool has_tile = tile < total_tiles;
+  unsigned long long base = 0;   // kPrefixMasks / kPrefixSums: read after the barrier below
+  uint32_t acc = 0;
+  // the records of all earlier tiles: from the scan, from the per-chunk
+  // counts (one round of loads, added up once the image entries are on
+  // their way), or (few chunks) from the masks
+  constexpr int U = kSumChunks / 256;
+  uint32_t cs[U];
+  if constexpr (PREFIX == kPrefixBase) base = chunk_base[chunk];
+  if constexpr (PREFIX == kPrefixSums) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = (uint32_t)tid + 256u * (uint32_t)u;
+      cs[u] = chunk_sum[i < chunk ? i : 0u];
+    }
+  }
+  if constexpr (PREFIX == kPrefixMasks) acc = lane_sum<8>(masks, c0, tid);
   const unsigned long long m_raw = masks[has_tile ? tile : 0u];
-  const uint32_t k0 = chunk_img ? chunk_img[chunk] : 0u;
   const int nk = (int)min<uint32_t>((uint32_t)kChunkImgs, n_imgs - k0);
   const ImgDev im = imgs[k0 + (uint32_t)min(tid, nk - 1)];
-  unsigned long long base;
-  if (chunk_base) {
-    base = chunk_base[chunk];
-  } else {
-    // the records of all earlier tiles, counted here: from the per-chunk
-    // counts when there are some, else (few chunks) from the masks
-    unsigned long long acc = chunk_sum ? lane_sum(chunk_sum, (uint64_t)chunk, tid)
-                                       : lane_sum(masks, c0, tid);
+  if constexpr (PREFIX == kPrefixSums) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    for (int u = 0; u < U; ++u) acc += (uint32_t)tid + 256u * (uint32_t)u < chunk ? cs[u] : 0u;
+  }
+  if constexpr (PREFIX != kPrefixBase) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += (uint32_t)__shfl_xor((int)acc, off);
     if (lane == 0) s_red[wave] = acc;
-    base = 0;   // read after the barrier below
   }
   if (tid < nk) {
     s_tf[tid] = im.tile_first;
@@ -155,7 +181,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ImgDev* imgs, uint32
     s_wf[tid] = im.wg_first;
   }
   __syncthreads();
-  if (!chunk_base) base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+  if constexpr (PREFIX != kPrefixBase) base = (unsigned long long)s_red[0] + s_red[1] + s_red[2] + s_red[3];
   const int nt = gx * gy;
   unsigned long long m = 0ull, slot = 0ull;
   uint32_t stride = 0;   // slots between cells of the tile
@@ -239,6 +265,21 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int PREFIX>
+static void launch_scatter_as(unsigned sgrid, const ImgDev* imgs, uint32_t n_imgs, const uint32_t* chunk_img,
+                              uint64_t total_tiles, unsigned grid, int cells, TileShape shape, const uint64_t* masks,
+                              const uint32_t* chunk_sum, const uint64_t* chunk_base, const uint4* staging, uint4* out,
+                              uint64_t cap, uint64_t* offsets, hipStream_t s) {
+  if (chunk_img)
+    hipLaunchKernelGGL((scatter_kernel<PREFIX, true>), dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img,
+                       total_tiles, grid, cells, shape.gx, shape.gy, masks, chunk_sum, chunk_base, staging, out, cap,
+                       offsets);
+  else
+    hipLaunchKernelGGL((scatter_kernel<PREFIX, false>), dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img,
+                       total_tiles, grid, cells, shape.gx, shape.gy, masks, chunk_sum, chunk_base, staging, out, cap,
+                       offsets);
+}
+
 hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* chunk_img, uint64_t total_tiles,
                           int cells, TileShape shape, const uint64_t* masks, uint32_t* chunk_sum,
                           uint64_t* chunk_base, const uint4* staging, uint4* out, uint64_t cap, uint64_t* offsets,
@@ -247,23 +288,20 @@ hipError_t launch_scatter(const ImgDev* imgs, uint32_t n_imgs, const uint32_t* c
   const unsigned sgrid = grid < kScatterGroups ? grid : kScatterGroups;
   if (grid <= kSmallChunks) {
     // one kernel: each chunk counts the records before it from the masks
-    hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
-                       cells, shape.gx, shape.gy, masks, (const uint32_t*)nullptr, (const uint64_t*)nullptr,
-                       staging, out, cap, offsets);
+    launch_scatter_as<kPrefixMasks>(sgrid, imgs, n_imgs, chunk_img, total_tiles, grid, cells, shape, masks, nullptr,
+                                    nullptr, staging, out, cap, offsets, s);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(kChunkTiles), 0, s, masks, total_tiles, chunk_sum);
   if (grid <= kSumChunks) {
     // each chunk adds up the counts of the chunks before it
-    hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
-                       cells, shape.gx, shape.gy, masks, (const uint32_t*)chunk_sum, (const uint64_t*)nullptr,
-                       staging, out, cap, offsets);
+    launch_scatter_as<kPrefixSums>(sgrid, imgs, n_imgs, chunk_img, total_tiles, grid, cells, shape, masks, chunk_sum,
+                                   nullptr, staging, out, cap, offsets, s);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, chunk_sum, grid, chunk_base);
-  hipLaunchKernelGGL(scatter_kernel, dim3(sgrid), dim3(256), 0, s, imgs, n_imgs, chunk_img, total_tiles, grid,
-                     cells, shape.gx, shape.gy, masks, (const uint32_t*)nullptr, (const uint64_t*)chunk_base,
-                     staging, out, cap, offsets);
+  launch_scatter_as<kPrefixBase>(sgrid, imgs, n_imgs, chunk_img, total_tiles, grid, cells, shape, masks, nullptr,
+                                 chunk_base, staging, out, cap, offsets, s);
   return hipGetLastError();
 }
 

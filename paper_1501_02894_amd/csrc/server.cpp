@@ -514,7 +514,9 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   // a quarter of the budget holds tile slots (records + masks), the rest
   // images, outputs and ordering scratch
   const size_t tile_bytes = (size_t)(s->cells + 1) * 16 + 8;   // record slots and mask
-  const size_t tiles_cap = (hbm_budget / 4) / tile_bytes;
+  size_t tiles_cap = (hbm_budget / 4) / tile_bytes;
+  // the 2 x 2 level's list holds 32-bit record slots
+  if (s->ext) tiles_cap = std::min<size_t>(tiles_cap, ((1ull << 32) - 1) / (size_t)(s->cells + 1));
   const size_t byte_budget = hbm_budget - tiles_cap * tile_bytes;
   (void)hipSetDevice(device);
   bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess &&
