@@ -432,9 +432,10 @@ fe_status fe_get_tile_shape(fe_ctx* ctx, uint32_t b_max, uint32_t b_min, uint32_
 /*
  * Autotuner: encode the given batch (as fe_encode_batch, into the caller's
  * d_out / d_offsets) `reps` times with every built tile shape for
- * (b_max, b_min), time the fused kernel with HIP events on `stream`, and
- * select the fastest for this context.  Writes the chosen shape and its
- * mean kernel time in milliseconds.  Waits for the device.
+ * (b_max, b_min), in two rounds over the shapes, time the fused kernel with
+ * HIP events on `stream`, and select the shape with the least mean kernel
+ * time (the better of its two rounds) for this context.  Writes the chosen
+ * shape and that time in milliseconds.  Waits for the device.
  */
 fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs, const fe_params* params,
                       fe_transform* d_out, size_t cap, uint64_t* d_offsets, uint32_t reps, uint32_t* gx,

@@ -53,16 +53,31 @@ struct Geo {
   // the same row of different tiles falls in different banks.
   static constexpr int TPITCH = BMAX;                         // tile pixel row pitch (bytes)
   static constexpr int TSTRIDE = BMAX * BMAX + 4;             // tile stride (bytes)
-  static constexpr int RWA = ((GX + 1) * BMAX + 6 + 7) & ~7;  // region width bound (px)
-  static constexpr int RHA = (GY + 1) * BMAX + 8;             // region height bound (px)
+  // The staged region is the union of the tiles' co-centred domains,
+  // (GX + 1) x (GY + 1) tiles, with its origin rounded down to 8 pixels.
+  // For b_max >= 16 the origin X0 - b_max / 2 (or its clamp to the image) is
+  // a multiple of 8 already, so the bounds are exact.
+  static constexpr bool EXACT = BMAX >= 16;
+  static constexpr int RWA = EXACT ? (GX + 1) * BMAX : ((GX + 1) * BMAX + 6 + 7) & ~7;  // region width bound (px)
+  static constexpr int RHA = EXACT ? (GY + 1) * BMAX : (GY + 1) * BMAX + 8;             // region height bound (px)
   static constexpr int HW = RWA / 2, HH = RHA / 2;            // H0 region bounds
-  static constexpr int HP = HW + 8;                           // H0 row pitch
-  static constexpr int TP = ((HH + 3) & ~3) + 8;              // H0^T row pitch
-  static constexpr int IMG_W = NT * TSTRIDE / 4 + 4;          // dwords
   static constexpr int HH4 = (HH + 3) & ~3;                   // H0 rows, multiple of 4
+  // Row pitches of H0 and H0^T: an odd number of dwords, so that the rows
+  // a range's window spans start in different banks.
+  static constexpr int odd_pitch(int w) { return ((w / 4 + 1) & 1) ? w + 4 : w + 8; }
+  static constexpr int HP = EXACT ? odd_pitch(HW) : HW + 8;   // H0 row pitch
+  static constexpr int TP = EXACT ? odd_pitch(HH4) : HH4 + 8; // H0^T row pitch
+  static constexpr int IMG_W = NT * TSTRIDE / 4 + 4;          // dwords
   static constexpr int H0_W = HH4 * HP / 4 + 4;
   static constexpr int H0T_W = HW * TP / 4 + 4;
   static_assert(NT % 4 == 0 && NT <= 256, "tiles per workgroup: a multiple of 4, at most one per lane");
+  // Moments of a short list, summed over the waves.  Below b_max = 32 only
+  // the top level has short lists (its list is the block's tiles, at most
+  // NT), and they are summed before that level writes its failed ranges, so
+  // the sums share their words with the lists of failed ranges.
+  static constexpr bool SHARE = BMAX <= 16;
+  static constexpr int PW = SHARE ? (NT <= 64 ? NT : 1) : 64;    // sums per moment
+  static constexpr int LIST_W = SHARE ? (2 * PCAP > 12 * PW ? 2 * PCAP : 12 * PW) : 2 * PCAP + 12 * PW;
 };
 
 struct Region {
@@ -266,10 +281,13 @@ struct Lds {
   uint32_t h0[G::H0_W];
   uint32_t h0t[G::H0T_W];
   uint32_t top[G::NT];             // level-1 list: the block's tiles inside the image
-  uint32_t par[2][G::PCAP];        // failed ranges of two consecutive levels (list entries)
-  uint32_t part[12][64];           // moments of a short list, summed over the waves
+  // failed ranges of two consecutive levels (list entries), and the
+  // moments of a short list summed over the waves (see Geo::SHARE)
+  uint32_t lists[G::LIST_W];
   uint32_t cnt[L + 1];             // per level: ranges that failed (parents of the next list)
   unsigned long long mask[G::NT];
+  __device__ __forceinline__ uint32_t* par(int k) { return lists + k * G::PCAP; }
+  __device__ __forceinline__ uint32_t* part(int j) { return lists + (G::SHARE ? 0 : 2 * G::PCAP) + j * G::PW; }
 };
 
 // DPP: every lane of a quad reads quad lane Q's value, or the sum over its quad.
@@ -386,8 +404,8 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
   // tiles inside the image, listed by the kernel before its barrier
   int n = bg.gx * bg.gy;
   for (int lev = 1; lev <= L; ++lev) {
-    const uint32_t* ppar = sm.par[(lev - 1) & 1];   // parents of this level's ranges
-    uint32_t* npar = sm.par[lev & 1];               // this level's failed ranges
+    const uint32_t* ppar = sm.par((lev - 1) & 1);   // parents of this level's ranges
+    uint32_t* npar = sm.par(lev & 1);               // this level's failed ranges
     uint32_t* nfail = &sm.cnt[lev];                 // zeroed by the kernel
     const bool last = lev == L && !EXT;   // EXT: the 4 x 4 level is tested too
     const int B = BMAX >> (lev - 1);
@@ -554,7 +572,7 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
           team_reduce(acc, tin);
           if (e < n && t == 0) {
 #pragma unroll
-            for (int j = 0; j < 12; ++j) atomicAdd(&sm.part[j][e], acc[j]);
+            for (int j = 0; j < 12; ++j) atomicAdd(sm.part(j) + e, acc[j]);
           }
         }
         __syncthreads();   // the list's moments are complete
@@ -563,8 +581,10 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
           uint32_t acc[12];
 #pragma unroll
           for (int j = 0; j < 12; ++j) {
-            acc[j] = sm.part[j][lane];   // zero beyond the list
-            sm.part[j][lane] = 0u;       // zero again for the next short list
+            acc[j] = lane < G::PW ? sm.part(j)[lane] : 0u;   // zero beyond the list
+            // zero again for the next short list (with SHARE there is none,
+            // and the words go on to hold this level's failed ranges)
+            if (!G::SHARE && lane < G::PW) sm.part(j)[lane] = 0u;
           }
           finish(lane, valid, acc);
         }
@@ -592,7 +612,7 @@ template <int BMAX, int L, int GX, int GY>
 __device__ __forceinline__ void block_start(const BlockGeo& bg, Lds<BMAX, L, GX, GY>& sm, int tid) {
   using G = Geo<BMAX, L, GX, GY>;
   for (int t = tid; t < G::NT; t += 256) sm.mask[t] = 0ull;
-  for (int t = tid; t < 12 * 64; t += 256) (&sm.part[0][0])[t] = 0u;
+  for (int t = tid; t < 12 * G::PW; t += 256) sm.part(0)[t] = 0u;
   if (tid <= L) sm.cnt[tid] = 0u;
   // level-1 list: the block's tiles inside the image, row-major (gx gy <= NT <= 256)
   if (tid < bg.gx * bg.gy) {
@@ -661,8 +681,8 @@ static hipError_t launch_one(const EncodeArgs& a, hipStream_t s) {
   X(4, 1, 16, 16) X(4, 1, 32, 8)                                                        \
   X(8, 1, 16, 8) X(8, 1, 8, 8) X(8, 2, 8, 8) X(8, 2, 16, 4) X(8, 2, 4, 4) X(8, 2, 8, 4)  \
   X(16, 1, 8, 4) X(16, 1, 4, 4) X(16, 2, 8, 4) X(16, 2, 4, 4) X(16, 2, 8, 2)             \
-  X(16, 3, 8, 7) X(16, 3, 8, 8) X(16, 3, 8, 4) X(16, 3, 4, 4) X(16, 3, 16, 2)            \
-  X(16, 3, 8, 2) X(16, 3, 4, 2) X(16, 3, 16, 4) X(16, 3, 8, 6)                          \
+  X(16, 3, 8, 8) X(16, 3, 8, 7) X(16, 3, 8, 6) X(16, 3, 8, 4) X(16, 3, 4, 4)             \
+  X(16, 3, 16, 2) X(16, 3, 8, 2) X(16, 3, 4, 2) X(16, 3, 16, 4)                         \
   X(32, 1, 4, 2) X(32, 1, 2, 2) X(32, 2, 4, 2) X(32, 2, 2, 2) X(32, 3, 4, 2)             \
   X(32, 3, 2, 2) X(32, 4, 4, 4) X(32, 4, 4, 2) X(32, 4, 2, 2) X(32, 4, 8, 1) X(32, 4, 4, 1)
 
@@ -686,7 +706,7 @@ hipError_t launch_mns_tiles(int b_max, int levels, TileShape shape, const Encode
 hipError_t launch_mns_tiles_ext(int b_max, int levels, TileShape shape, const EncodeArgs& a, hipStream_t s) {
   // the default shapes of 16 -> 4, 8 -> 4 and 4 -> 4, and the smallest of
   // the first two (for calls with few tiles)
-  if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 7) return launch_one<16, 3, 8, 7, true>(a, s);
+  if (b_max == 16 && levels == 3 && shape.gx == 8 && shape.gy == 8) return launch_one<16, 3, 8, 8, true>(a, s);
   if (b_max == 16 && levels == 3 && shape.gx == 4 && shape.gy == 2) return launch_one<16, 3, 4, 2, true>(a, s);
   if (b_max == 8 && levels == 2 && shape.gx == 8 && shape.gy == 8) return launch_one<8, 2, 8, 8, true>(a, s);
   if (b_max == 8 && levels == 2 && shape.gx == 4 && shape.gy == 4) return launch_one<8, 2, 4, 4, true>(a, s);
