@@ -224,6 +224,45 @@ def test_ordering_paths(torch_dev, ctx, H, W, b_max, b_min, thr, path):
     assert_same_stream(got, want)
 
 
+def test_context_reuse_across_ordering_paths(torch_dev):
+    """One context encodes a sequence whose chunk counts go up and down (the
+    one-kernel ordering, summed chunk counts, the scan beyond 4096 chunks, a
+    16 -> 2 tree, a batch), so its scratch buffers grow and are reused with
+    stale contents; every stream must equal the same call on a fresh
+    context."""
+    cases = [
+        ("single 512", [synth.noise_1f(512, 512, 301)], 16, 4, [300, 200]),
+        ("scan 4160 chunks", [synth.noise_1f(4096, 4160, 302)], 4, 4, []),
+        ("single 256", [synth.piecewise_smooth(256, 256, 303)], 16, 4, [300, 200]),
+        ("16 -> 2", [synth.noise_1f(640, 384, 304)], 16, 2, [300, 200, 100]),
+        ("batch", [synth.noise_1f(256 + 64 * k, 512, 305 + k) for k in range(6)], 16, 4, [300, 200]),
+        ("sums 128 chunks", [synth.noise_1f(1024, 2048, 311)], 8, 4, [400]),
+        ("single 512 again", [synth.noise_1f(512, 512, 301)], 16, 4, [300, 200]),
+    ]
+    shared = fb.Context(0)
+    try:
+        for name, imgs, b_max, b_min, thr in cases:
+            log(f"context reuse: {name}")
+            t_imgs = [dev(torch_dev, im) for im in imgs]
+            fresh = fb.Context(0)
+            try:
+                if len(imgs) == 1:
+                    got = fb.to_records(shared.encode(t_imgs[0], b_max, b_min, thr))
+                    want = fb.to_records(fresh.encode(t_imgs[0], b_max, b_min, thr))
+                else:
+                    o1, f1, n1 = shared.encode_batch(t_imgs, b_max, b_min, thr)
+                    o2, f2, n2 = fresh.encode_batch(t_imgs, b_max, b_min, thr)
+                    torch_dev.cuda.synchronize()
+                    assert f1.cpu().numpy().tolist() == f2.cpu().numpy().tolist(), name
+                    got, want = fb.to_records(o1[:n1]), fb.to_records(o2[:n2])
+                torch_dev.cuda.synchronize()
+            finally:
+                fresh.close()
+            assert got.tobytes() == want.tobytes(), name
+    finally:
+        shared.close()
+
+
 # ------------------------------------------------------------------ batch
 def test_encode_batch_matches_single(torch_dev, ctx):
     rng = np.random.default_rng(5)
