@@ -113,6 +113,7 @@ struct Request {
   size_t hout_off = 0, hout_len = 0;     // pinned host output: records, then 2 x u64 offsets
   int slot = -1;                         // admission slot: owns ev_copied / ev_done of that slot
   bool waited = false;                   // compute stream already waits on the copy event
+  bool fetching = false;                 // fe_server_poll is copying the records out (lock not held)
   ReqState state = ReqState::Queued;
   size_t n_out = 0;
   // submitted, admitted (image copy issued), first and last step launched,
@@ -149,6 +150,7 @@ struct fe_server {
   std::mutex mu;
   std::condition_variable cv, done_cv;
   std::deque<Request*> queued;
+  std::deque<Request*> ordering;         // ordering kernels queued on the compute stream, in launch order
   std::deque<uint64_t> completions;      // finished ids not yet reported by fe_server_wait
   std::vector<Request*> active;          // admitted, not yet done
   std::map<uint64_t, Request*> all;      // by id, until fetched
@@ -416,8 +418,12 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
   s->steps++;
   s->blocks_run += n;
   for (Request* r : finishing) {
-    if (e != hipSuccess) fail_request(r);
-    else r->state = ReqState::Ordering;
+    if (e != hipSuccess) {
+      fail_request(r);
+    } else {
+      r->state = ReqState::Ordering;
+      s->ordering.push_back(r);
+    }
   }
   if (e != hipSuccess)
     for (Request* r : ready) fail_request(r);
@@ -428,18 +434,25 @@ bool run_step(fe_server* s, std::unique_lock<std::mutex>& lk) {
 // Returns true on any progress.
 bool finish(fe_server* s) {
   bool any = false;
+  // the ordering kernels run in launch order on the compute stream, so the
+  // requests complete in that order: query from the oldest until one is
+  // still running (one event query per completion, not per request)
+  while (!s->ordering.empty()) {
+    Request* r = s->ordering.front();
+    if (r->state == ReqState::Ordering && hipEventQuery(s->ev_done[r->slot]) != hipSuccess) break;
+    s->ordering.pop_front();
+    if (r->state != ReqState::Ordering) continue;   // failed meanwhile
+    uint64_t total = 0;
+    memcpy(&total, s->host_base + r->hout_off + r->cap * 16 + 8, 8);
+    r->n_out = (size_t)total;
+    r->state = r->n_out <= r->cap ? ReqState::Done : ReqState::Failed;
+    if (r->state == ReqState::Failed) r->error = FE_ERR_DEVICE;
+    r->t_done = Clock::now();
+    s->completed++;
+    any = true;
+  }
   for (size_t i = 0; i < s->active.size();) {
     Request* r = s->active[i];
-    if (r->state == ReqState::Ordering && hipEventQuery(s->ev_done[r->slot]) == hipSuccess) {
-      uint64_t total = 0;
-      memcpy(&total, s->host_base + r->hout_off + r->cap * 16 + 8, 8);
-      r->n_out = (size_t)total;
-      r->state = r->n_out <= r->cap ? ReqState::Done : ReqState::Failed;
-      if (r->state == ReqState::Failed) r->error = FE_ERR_DEVICE;
-      r->t_done = Clock::now();
-      s->completed++;
-      any = true;
-    }
     if (r->state == ReqState::Done || r->state == ReqState::Failed) {
       // the device side is no longer needed; the host output stays until fetched
       if (r->dev_len) s->dev_arena.release(r->dev_off, r->dev_len);
@@ -694,10 +707,11 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
                          double* latency_ms) {
   fe::clear_error();
   if (!s || !done) return fe::fail(FE_ERR_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> g(s->mu);
+  std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->all.find(req);
   if (it == s->all.end()) return fe::fail(FE_ERR_INVALID, "unknown request %llu", (unsigned long long)req);
   Request* r = it->second;
+  if (r->fetching) return fe::fail(FE_ERR_BUSY, "request %llu is being fetched by another call", (unsigned long long)req);
   if (r->state == ReqState::Failed) {
     const fe_status e = r->error;
     if (std::find(s->active.begin(), s->active.end(), r) == s->active.end()) {
@@ -716,9 +730,16 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
   if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
   if (h_out) {
     if (cap < r->n_out) return fe::fail(FE_ERR_CAPACITY, "output holds %zu transforms, %zu needed", cap, r->n_out);
-    memcpy(h_out, s->host_base + r->hout_off, r->n_out * sizeof(fe_transform));
+    // copy without the lock (the worker keeps stepping meanwhile); the
+    // request's pinned output stays reserved until it is forgotten below
+    r->fetching = true;
+    const uint8_t* src = s->host_base + r->hout_off;
+    const size_t bytes = r->n_out * sizeof(fe_transform);
+    lk.unlock();
+    memcpy(h_out, src, bytes);
+    lk.lock();
     forget(s, r);
-    s->all.erase(it);
+    s->all.erase(req);
     delete r;
   }
   return FE_OK;
