@@ -463,7 +463,8 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
             if rid is None:
                 continue
             st = srv.request_times(rid)
-            ok, recs, l = srv.poll(rid)
+            recs, l = srv.result(rid)     # the records in the server's pinned memory, no copy
+            srv.release(rid)
             while rid not in index:      # the submitter has not recorded it yet
                 time.sleep(0)
             i = index[rid]

@@ -502,6 +502,18 @@ fe_status fe_server_poll(fe_server* server, uint64_t req, fe_transform* h_out, s
                          int* done, double* latency_ms);
 fe_status fe_server_wait(fe_server* server, uint32_t timeout_us, uint64_t* req);
 /*
+ * Zero-copy access to a finished request's records: *recs points at its
+ * *n records (stream order, as fe_server_poll would copy them) in the
+ * server's pinned host memory, and stays valid until
+ * fe_server_release(server, req), which frees them and forgets the id.
+ * FE_ERR_BUSY while the request runs; FE_ERR_DEVICE (request released) if
+ * it failed; FE_ERR_INVALID for an unknown id.  A request is released either
+ * by fe_server_poll with h_out or by fe_server_release, not both.
+ */
+fe_status fe_server_result(fe_server* server, uint64_t req, const fe_transform** recs, size_t* n,
+                           double* latency_ms);
+fe_status fe_server_release(fe_server* server, uint64_t req);
+/*
  * Where a request's latency went (execution; no passage of the paper): the
  * times, in milliseconds after its submission, at which request `req` was
  * admitted (its image copy issued), had its first and its last step

@@ -115,6 +115,9 @@ _SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_uint64)]),
     "fe_server_submit_pinned": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, ctypes.POINTER(fe_params),
                                                ctypes.POINTER(ctypes.c_uint64)]),
+    "fe_server_result": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_VP), ctypes.POINTER(_SZ),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "fe_server_release": (ctypes.c_int, [_VP, ctypes.c_uint64]),
     "fe_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _SZ, ctypes.POINTER(_SZ), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_double)]),
     "fe_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
@@ -521,6 +524,23 @@ def fe_server_poll(server: int, req: int, fetch: bool = True):
     return True, out[: n.value], lat.value
 
 
+def fe_server_result(server: int, req: int):
+    """(records, latency_ms) of a done request: a numpy view of its records
+    in the server's pinned host memory, valid until fe_server_release."""
+    ptr = _VP()
+    n = _SZ(0)
+    lat = ctypes.c_double(0)
+    _check(load().fe_server_result(server, req, ctypes.byref(ptr), ctypes.byref(n), ctypes.byref(lat)))
+    if n.value == 0:
+        return np.empty(0, TRANSFORM_DTYPE), lat.value
+    buf = (ctypes.c_uint8 * (16 * n.value)).from_address(ptr.value)
+    return np.frombuffer(buf, dtype=TRANSFORM_DTYPE), lat.value
+
+
+def fe_server_release(server: int, req: int) -> None:
+    _check(load().fe_server_release(server, req))
+
+
 def fe_server_wait(server: int, timeout_us: int):
     """Id of the next finished request, or None if none finished in time."""
     req = ctypes.c_uint64(0)
@@ -573,6 +593,12 @@ class Server:
 
     def wait(self, timeout_us=1000):
         return fe_server_wait(self.handle, timeout_us)
+
+    def result(self, req):
+        return fe_server_result(self.handle, req)
+
+    def release(self, req):
+        fe_server_release(self.handle, req)
 
     def request_times(self, req):
         return fe_server_request_times(self.handle, req)

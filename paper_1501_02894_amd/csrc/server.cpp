@@ -745,6 +745,48 @@ fe_status fe_server_poll(fe_server* s, uint64_t req, fe_transform* h_out, size_t
   return FE_OK;
 }
 
+fe_status fe_server_result(fe_server* s, uint64_t req, const fe_transform** recs, size_t* n, double* latency_ms) {
+  fe::clear_error();
+  if (!s || !recs || !n) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(req);
+  if (it == s->all.end()) return fe::fail(FE_ERR_INVALID, "unknown request %llu", (unsigned long long)req);
+  Request* r = it->second;
+  if (r->fetching) return fe::fail(FE_ERR_BUSY, "request %llu is being fetched by another call", (unsigned long long)req);
+  if (r->state == ReqState::Failed) {
+    const fe_status e = r->error;
+    if (std::find(s->active.begin(), s->active.end(), r) == s->active.end()) {
+      forget(s, r);
+      s->all.erase(it);
+      delete r;
+    }
+    return fe::fail(e, "request failed on the device");
+  }
+  if (r->state != ReqState::Done) return fe::fail(FE_ERR_BUSY, "request %llu is not done", (unsigned long long)req);
+  *recs = reinterpret_cast<const fe_transform*>(s->host_base + r->hout_off);
+  *n = r->n_out;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  return FE_OK;
+}
+
+fe_status fe_server_release(fe_server* s, uint64_t req) {
+  fe::clear_error();
+  if (!s) return fe::fail(FE_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(req);
+  if (it == s->all.end()) return fe::fail(FE_ERR_INVALID, "unknown request %llu", (unsigned long long)req);
+  Request* r = it->second;
+  if (r->fetching) return fe::fail(FE_ERR_BUSY, "request %llu is being fetched by another call", (unsigned long long)req);
+  if (r->state != ReqState::Done && r->state != ReqState::Failed)
+    return fe::fail(FE_ERR_BUSY, "request %llu is not finished", (unsigned long long)req);
+  if (std::find(s->active.begin(), s->active.end(), r) != s->active.end())
+    return fe::fail(FE_ERR_BUSY, "request %llu is still being retired", (unsigned long long)req);
+  forget(s, r);
+  s->all.erase(it);
+  delete r;
+  return FE_OK;
+}
+
 fe_status fe_server_request_times(fe_server* s, uint64_t req, double* ms, uint32_t n) {
   fe::clear_error();
   if (!s || (n && !ms)) return fe::fail(FE_ERR_INVALID, "NULL argument");

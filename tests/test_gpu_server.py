@@ -251,3 +251,34 @@ def test_server_per_request_params(torch_dev, ctx, b_min, extra):
         if im.size <= 128 * 128:
             o = mns.encode(im, 16, b_min, s["thresholds"], phase2=s["phase2"], isometries=not s["identity_only"])
             assert res[k][0].tobytes() == np.ascontiguousarray(o).tobytes(), k
+
+
+def test_server_zero_copy_result(torch_dev, ctx):
+    """fe_server_result hands out a finished request's records in the
+    server's pinned memory (the same bytes fe_server_poll copies), valid
+    until fe_server_release forgets the id; a running request is busy."""
+    imgs = mixed_images(8, 51, 64, 512)
+    got = {}
+    with fb.Server(16, 4, THR, max_slots=8, step_blocks=64) as srv:
+        big = srv.submit(synth.noise_1f(1024, 1024, 52))
+        try:
+            srv.result(big)                      # almost surely still running
+        except fb.FeError as e:
+            assert e.status == fb.FE_ERR_BUSY
+        reqs = [srv.submit(im) for im in imgs]
+        t0 = time.time()
+        while len(got) < len(reqs) + 1:
+            rid = srv.wait(10000)
+            assert time.time() - t0 < 60, "server did not finish"
+            if rid is None:
+                continue
+            recs, lat = srv.result(rid)
+            assert lat > 0
+            got[rid] = recs.copy()
+            srv.release(rid)
+            with pytest.raises(fb.FeError) as ei:
+                srv.result(rid)
+            assert ei.value.status == fb.FE_ERR_INVALID
+    for k, r in enumerate(reqs):
+        assert got[r].tobytes() == alone(torch_dev, ctx, imgs[k]).tobytes(), k
+    assert got[big].tobytes() == alone(torch_dev, ctx, synth.noise_1f(1024, 1024, 52)).tobytes()
