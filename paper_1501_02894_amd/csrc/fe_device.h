@@ -77,18 +77,11 @@ __device__ __forceinline__ void lds_row_at(const uint8_t* p, uint32_t (&o)[Q]) {
 // d[j][i], d[B-1-j][i], d[j][B-1-i], d[B-1-j][B-1-i] give, per row i
 // (i' = B-1-i):  e0 r_i.d_i, e1 rrev_i.d_i, e2 r_i.d_i', e3 rrev_i.d_i',
 // e4 r_i.dT_i, e5 rrev_i.dT_i, e6 r_i.dT_i', e7 rrev_i.dT_i'.
-template <int B, bool ALIGNED>
-__device__ __forceinline__ void accumulate_rows(const uint8_t* rap, const uint8_t* rbp, const uint8_t* dap,
-                                                const uint8_t* dbp, const uint8_t* tap, const uint8_t* tbp,
-                                                uint32_t (&a)[12]) {
-  constexpr int Q = B / 4;
-  uint32_t ra[Q], rb[Q], da[Q], db[Q], ta[Q], tb[Q];
-  lds_row_at<Q, true>(rap, ra);
-  lds_row_at<Q, true>(rbp, rb);
-  lds_row_at<Q, ALIGNED>(dap, da);
-  lds_row_at<Q, ALIGNED>(dbp, db);
-  lds_row_at<Q, ALIGNED>(tap, ta);
-  lds_row_at<Q, ALIGNED>(tbp, tb);
+template <int Q>
+__device__ __forceinline__ void accumulate_words(const uint32_t (&ra)[Q], const uint32_t (&rb)[Q],
+                                                 const uint32_t (&da)[Q], const uint32_t (&db)[Q],
+                                                 const uint32_t (&ta)[Q], const uint32_t (&tb)[Q],
+                                                 uint32_t (&a)[12]) {
   const uint32_t ones = 0x01010101u;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -108,6 +101,55 @@ __device__ __forceinline__ void accumulate_rows(const uint8_t* rap, const uint8_
     a[10] = dot4(xa, tb[q], dot4(xb, ta[q], a[10]));
     a[11] = dot4(ya, tb[q], dot4(yb, ta[q], a[11]));
   }
+}
+
+template <int B, bool ALIGNED>
+__device__ __forceinline__ void accumulate_rows(const uint8_t* rap, const uint8_t* rbp, const uint8_t* dap,
+                                                const uint8_t* dbp, const uint8_t* tap, const uint8_t* tbp,
+                                                uint32_t (&a)[12]) {
+  constexpr int Q = B / 4;
+  uint32_t ra[Q], rb[Q], da[Q], db[Q], ta[Q], tb[Q];
+  lds_row_at<Q, true>(rap, ra);
+  lds_row_at<Q, true>(rbp, rb);
+  lds_row_at<Q, ALIGNED>(dap, da);
+  lds_row_at<Q, ALIGNED>(dbp, db);
+  lds_row_at<Q, ALIGNED>(tap, ta);
+  lds_row_at<Q, ALIGNED>(tbp, tb);
+  accumulate_words<Q>(ra, rb, da, db, ta, tb, a);
+}
+
+// Q dwords of an LDS row that starts sh bytes (0..3) after the dword w.
+template <int Q, bool ALIGNED>
+__device__ __forceinline__ void lds_row_sh(const uint32_t* w, uint32_t sh, uint32_t (&o)[Q]) {
+  if constexpr (ALIGNED) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o[q] = w[q];
+  } else {
+    uint32_t v[Q + 1];
+#pragma unroll
+    for (int q = 0; q <= Q; ++q) v[q] = w[q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o[q] = __builtin_amdgcn_alignbyte(v[q + 1], v[q], sh);
+  }
+}
+
+// accumulate_rows for windows whose rows all share one byte shift: the
+// range rows ra, rb and the dword before each window row (da, db: H0, shd
+// bytes in; ta, tb: H0^T, sht bytes in), so that the shifts and aligned
+// addresses are formed once per range rather than once per row.
+template <int B, bool ALIGNED>
+__device__ __forceinline__ void accumulate_rows_sh(const uint32_t* rap, const uint32_t* rbp, const uint32_t* dap,
+                                                   const uint32_t* dbp, const uint32_t* tap, const uint32_t* tbp,
+                                                   uint32_t shd, uint32_t sht, uint32_t (&a)[12]) {
+  constexpr int Q = B / 4;
+  uint32_t ra[Q], rb[Q], da[Q], db[Q], ta[Q], tb[Q];
+  lds_row_sh<Q, true>(rap, 0u, ra);
+  lds_row_sh<Q, true>(rbp, 0u, rb);
+  lds_row_sh<Q, ALIGNED>(dap, shd, da);
+  lds_row_sh<Q, ALIGNED>(dbp, shd, db);
+  lds_row_sh<Q, ALIGNED>(tap, sht, ta);
+  lds_row_sh<Q, ALIGNED>(tbp, sht, tb);
+  accumulate_words<Q>(ra, rb, da, db, ta, tb, a);
 }
 
 // The same for the range at byte offset r_off of `img` (row pitch rp), the
@@ -282,17 +324,19 @@ __device__ __forceinline__ uint4 make_record(int x, int y, int dx, int dy, int l
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Four round-half-up 2x2 means of an 8-wide, 2-row pixel group:
-// a0/a1 = row 0 pixels 0-3 / 4-7, b0/b1 = row 1.  Sums of two pixel pairs
-// are formed in 16-bit fields (even bytes masked, odd bytes moved down by a
-// byte permute); each field is below 2^10, so after the shift by 2 its low
-// byte is the mean and a final permute packs the four bytes.
+// a0/a1 = row 0 pixels 0-3 / 4-7, b0/b1 = row 1.  Column pairs are first
+// averaged down (v_lerp_u8, per byte floor((a + b) / 2)); with u_e, u_o the
+// averages of the even and odd column of an output pixel and c_e, c_o the
+// bits they dropped ((a ^ b) & 1), the mean (sum + 2) >> 2 equals
+// (u_e + (c_e & c_o) + u_o + 1) >> 1, a second v_lerp_u8 with rounding bit
+// 1 (u_e + 1 cannot overflow: c_e = 1 implies u_e <= 254).
 __device__ __forceinline__ uint32_t mean2x2_x4(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
-  const uint32_t M = 0x00FF00FFu, ODD = 0x0c030c01u;   // bytes 1, 3 -> 0, 2
-  const uint32_t s0 = (a0 & M) + (b0 & M) + __builtin_amdgcn_perm(0u, a0, ODD) + __builtin_amdgcn_perm(0u, b0, ODD) +
-                      0x00020002u;
-  const uint32_t s1 = (a1 & M) + (b1 & M) + __builtin_amdgcn_perm(0u, a1, ODD) + __builtin_amdgcn_perm(0u, b1, ODD) +
-                      0x00020002u;
-  return __builtin_amdgcn_perm(s1 >> 2, s0 >> 2, 0x06040200u);
+  const uint32_t u0 = __builtin_amdgcn_lerp(a0, b0, 0u), u1 = __builtin_amdgcn_lerp(a1, b1, 0u);
+  const uint32_t x0 = a0 ^ b0, x1 = a1 ^ b1;
+  constexpr uint32_t EVEN = 0x06040200u, ODD = 0x07050301u;   // bytes 0, 2 of lo, then of hi
+  const uint32_t ue = __builtin_amdgcn_perm(u1, u0, EVEN), uo = __builtin_amdgcn_perm(u1, u0, ODD);
+  const uint32_t cc = __builtin_amdgcn_perm(x1, x0, EVEN) & __builtin_amdgcn_perm(x1, x0, ODD) & 0x01010101u;
+  return __builtin_amdgcn_lerp(ue + cc, uo, 0x01010101u);
 }
 
 }  // namespace fe

@@ -163,6 +163,10 @@ __device__ __forceinline__ BlockGeo block_geo(const BlockDesc& d) {
 // than flat_load, which would also occupy the LDS counter).
 typedef __attribute__((address_space(1))) const uint32_t gu32;
 
+// Word 3 of a raw buffer resource on gfx9-family chips (gfx950 included):
+// 32-bit data format, no swizzle, no index stride.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Region staging.  A group is 8 x 8 pixels of the region (column group c8,
 // rows 8 g .. 8 g + 7), i.e. a 4 x 4 block of H0; lane `tid` owns groups
 // tid + 256 * it.  load() reads the lane's groups from the image into
@@ -181,6 +185,29 @@ struct Stage {
   }
 
   __device__ __forceinline__ void load(const BlockGeo& b, int tid) {
+    if constexpr (G::BMAXV >= 16) {
+      // Through a buffer resource based at the region origin, row r of a
+      // group is the scalar offset r * stride: no per-row address arithmetic
+      // in vector registers.  Needs every region offset below 2^31.
+      if ((uint64_t)G::RHA * b.stride < (1ull << 31)) {
+        const uint8_t* org = b.data + (size_t)b.rg.ay0 * b.stride + b.rg.ax0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(org), (short)0, (int)((uint32_t)G::RHA * b.stride), kBufferWord3);
+#pragma unroll
+        for (int it = 0; it < NG; ++it) {
+          int g, c8;
+          if (!owns(b, tid + 256 * it, g, c8)) continue;
+          const uint32_t voff = (uint32_t)(8 * g) * b.stride + 8u * (uint32_t)c8;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, (uint32_t)r * b.stride, 0);
+            v[it][r][0] = w[0];
+            v[it][r][1] = w[1];
+          }
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int it = 0; it < NG; ++it) {
       int g, c8;
@@ -229,8 +256,9 @@ struct Stage {
       if constexpr (G::BMAXV >= 8) {
         const int gy0 = b.rg.ay0 + 8 * g;
         if (gy0 >= b.rg.Y0 && gy0 < b.ty_end && x >= b.rg.X0 && x < b.tx_end) {
-          const int px = x - b.rg.X0, py = gy0 - b.rg.Y0;   // inside the tile block
-          const int t = (py / G::BMAXV) * G::GXV + px / G::BMAXV;
+          // inside the tile block, so non-negative
+          const uint32_t px = (uint32_t)(x - b.rg.X0), py = (uint32_t)(gy0 - b.rg.Y0);
+          const uint32_t t = (py / G::BMAXV) * G::GXV + px / G::BMAXV;
           uint32_t* dst = s_img + t * (G::TSTRIDE / 4) + (py % G::BMAXV) * (G::TPITCH / 4) + (px % G::BMAXV) / 4;
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
@@ -392,9 +420,6 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
   constexpr int LOG_BMAX = Log2<BMAX>::value;
   const Region& rg = bg.rg;
   const int tid = threadIdx.x;
-  const uint8_t* img_b = reinterpret_cast<const uint8_t*>(sm.img);
-  const uint8_t* h0_b = reinterpret_cast<const uint8_t*>(sm.h0);
-  const uint8_t* h0t_b = reinterpret_cast<const uint8_t*>(sm.h0t);
   unsigned long long* s_mask = sm.mask;
   uint4* const rec_base = a.staging + (uint64_t)bg.sblk * (uint64_t)(G::NT * (CE + 1));   // the block's record slots
   const int wave = tid >> 6, lane = tid & 63;
@@ -518,9 +543,12 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
           const int e = g * 64 + lane;
           const bool valid = e < n;
           const W w(range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1)), rg);
-          const uint8_t* r0 = img_b + w.roff;
-          const uint8_t* d0 = h0_b + w.doff;
-          const uint8_t* t0 = h0t_b + w.toff;
+          // dword-aligned row starts; every window row shares its byte shift
+          const uint32_t* r0 = sm.img + (w.roff >> 2);
+          const uint32_t* d0 = sm.h0 + (w.doff >> 2);
+          const uint32_t* t0 = sm.h0t + (w.toff >> 2);
+          const uint32_t shd = (uint32_t)w.doff & 3u, sht = (uint32_t)w.toff & 3u;
+          constexpr int RW = G::TPITCH / 4, HW4 = G::HP / 4, TW4 = G::TP / 4;
           uint32_t acc[12];
 #pragma unroll
           for (int j = 0; j < 12; ++j) acc[j] = 0u;
@@ -529,13 +557,15 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
           if constexpr (RP <= 2) {
 #pragma unroll
             for (int i = 0; i < RP; ++i)
-              accumulate_rows<BB, ALIGNED>(r0 + i * G::TPITCH, r0 + (BB - 1 - i) * G::TPITCH, d0 + i * G::HP,
-                                           d0 + (BB - 1 - i) * G::HP, t0 + i * G::TP, t0 + (BB - 1 - i) * G::TP, acc);
+              accumulate_rows_sh<BB, ALIGNED>(r0 + i * RW, r0 + (BB - 1 - i) * RW, d0 + i * HW4,
+                                              d0 + (BB - 1 - i) * HW4, t0 + i * TW4, t0 + (BB - 1 - i) * TW4, shd,
+                                              sht, acc);
           } else {
 #pragma unroll 1
             for (int i = 0; i < RP; ++i)
-              accumulate_rows<BB, ALIGNED>(r0 + i * G::TPITCH, r0 + (BB - 1 - i) * G::TPITCH, d0 + i * G::HP,
-                                           d0 + (BB - 1 - i) * G::HP, t0 + i * G::TP, t0 + (BB - 1 - i) * G::TP, acc);
+              accumulate_rows_sh<BB, ALIGNED>(r0 + i * RW, r0 + (BB - 1 - i) * RW, d0 + i * HW4,
+                                              d0 + (BB - 1 - i) * HW4, t0 + i * TW4, t0 + (BB - 1 - i) * TW4, shd,
+                                              sht, acc);
           }
           finish(e, valid, acc);
         }
@@ -551,23 +581,25 @@ __device__ __forceinline__ void process_block(const EncodeArgs& a, const LevelPa
           const int e = lane >> logt, t = lane & (tin - 1);
           const W w(range_ref<BB, BMAX, G::BMIN>(sm.top, ppar, min(e, n - 1)), rg);
           const int i0 = wr * tin + t, step = sw * tin;
-          const uint8_t* ra = img_b + w.roff + i0 * G::TPITCH;
-          const uint8_t* rb = img_b + w.roff + (BB - 1 - i0) * G::TPITCH;
-          const uint8_t* da = h0_b + w.doff + i0 * G::HP;
-          const uint8_t* db = h0_b + w.doff + (BB - 1 - i0) * G::HP;
-          const uint8_t* ta = h0t_b + w.toff + i0 * G::TP;
-          const uint8_t* tb = h0t_b + w.toff + (BB - 1 - i0) * G::TP;
+          constexpr int RW = G::TPITCH / 4, HW4 = G::HP / 4, TW4 = G::TP / 4;
+          const uint32_t shd = (uint32_t)w.doff & 3u, sht = (uint32_t)w.toff & 3u;
+          const uint32_t* ra = sm.img + (w.roff >> 2) + i0 * RW;
+          const uint32_t* rb = sm.img + (w.roff >> 2) + (BB - 1 - i0) * RW;
+          const uint32_t* da = sm.h0 + (w.doff >> 2) + i0 * HW4;
+          const uint32_t* db = sm.h0 + (w.doff >> 2) + (BB - 1 - i0) * HW4;
+          const uint32_t* ta = sm.h0t + (w.toff >> 2) + i0 * TW4;
+          const uint32_t* tb = sm.h0t + (w.toff >> 2) + (BB - 1 - i0) * TW4;
           uint32_t acc[12];
 #pragma unroll
           for (int j = 0; j < 12; ++j) acc[j] = 0u;
           for (int i = i0; i < RP; i += step) {
-            accumulate_rows<BB, ALIGNED>(ra, rb, da, db, ta, tb, acc);
-            ra += step * G::TPITCH;
-            rb -= step * G::TPITCH;
-            da += step * G::HP;
-            db -= step * G::HP;
-            ta += step * G::TP;
-            tb -= step * G::TP;
+            accumulate_rows_sh<BB, ALIGNED>(ra, rb, da, db, ta, tb, shd, sht, acc);
+            ra += step * RW;
+            rb -= step * RW;
+            da += step * HW4;
+            db -= step * HW4;
+            ta += step * TW4;
+            tb -= step * TW4;
           }
           team_reduce(acc, tin);
           if (e < n && t == 0) {

@@ -144,6 +144,30 @@ def test_encode_strided_input(torch_dev, ctx):
     assert_same_stream(got, mns.encode(img, 16, 4, [300, 200]))
 
 
+def test_encode_huge_pitch(torch_dev, ctx):
+    """A 32 MiB row pitch: the encoder reads a workgroup's region through a
+    buffer resource when the region spans under 2 GiB (tile shapes with 48
+    region rows) and through global addresses otherwise (80 rows and more);
+    every shape gives the oracle's stream."""
+    H, W, pitch = 48, 64, 1 << 25
+    img = synth.noise_1f(H, W, 57)
+    want = mns.encode(img, 16, 4, [300, 200])
+    buf = torch_dev.zeros((H - 1) * pitch + W, dtype=torch_dev.uint8, device="cuda")
+    for r in range(H):
+        buf[r * pitch:r * pitch + W].copy_(torch_dev.from_numpy(img[r].copy()))
+    t = buf.as_strided((H, W), (pitch, 1))
+    assert t.stride(0) == pitch
+    try:
+        for gx, gy in fb.fe_tile_shapes(16, 4):
+            log(f"  shape {gx}x{gy} pitch {pitch}")
+            fb.fe_set_tile_shape(ctx.handle, 16, 4, gx, gy)
+            got = fb.to_records(ctx.encode(t, 16, 4, [300, 200]))
+            assert_same_stream(got, want)
+    finally:
+        fb.fe_set_tile_shape(ctx.handle, 16, 4, 0, 0)
+    del t, buf
+
+
 @pytest.mark.parametrize("b_max,b_min,thr,H,W", [
     (16, 4, [300, 200], 320, 224), (16, 8, [300], 160, 96), (16, 16, [], 96, 48),
     (32, 4, [150, 100, 64], 256, 320), (32, 8, [200, 100], 192, 128), (32, 16, [200], 96, 64),
