@@ -421,8 +421,14 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
     percentiles (scheduled arrival -> records in host memory).  `pool` holds
     the request images as pinned host tensors; the server takes them without
     a host copy, the plain path copies each to the device itself."""
+    import gc
     import threading
     import torch
+    # a full collection over the bench's many live objects can stall the
+    # submitting thread for tens of milliseconds: move them out of the
+    # collector's reach for the run (both modes)
+    gc.collect()
+    gc.freeze()
     total = n_req + warmup
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, total))
@@ -495,6 +501,7 @@ def serve_run(fb, mode, pool, rate, n_req, warmup, seed, ctx=None):
             done_at[i] = now
             lat[i] = now - arrivals[i]
         stats = None
+    gc.unfreeze()
     m = slice(warmup, total)
     span = done_at[m].max() - arrivals[m].min()
     res = {"mode": mode, "rate": rate, "requests": n_req, "images_per_s": n_req / span,

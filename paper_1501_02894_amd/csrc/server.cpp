@@ -93,7 +93,9 @@ class Arena {
   size_t size_ = 0, used_ = 0, g_ = 1;
 };
 
-enum class ReqState { Queued, Running, Ordering, Done, Failed };
+// Queued -> Copying (image copy issued) -> Running (copy complete: steps take
+// its blocks) -> Ordering (last block launched) -> Done / Failed.
+enum class ReqState { Queued, Copying, Running, Ordering, Done, Failed };
 
 struct Request {
   uint64_t id = 0;
@@ -112,6 +114,8 @@ struct Request {
   size_t tile_base = 0, tile_len = 0;    // tile arena range
   size_t hout_off = 0, hout_len = 0;     // pinned host output: records, then 2 x u64 offsets
   int slot = -1;                         // admission slot: owns ev_copied / ev_done of that slot
+  int copy_stream = -1;                  // the copy stream of its image, while Copying
+  size_t copy_bytes = 0;
   bool waited = false;                   // compute stream already waits on the copy event
   bool fetching = false;                 // fe_server_poll is copying the records out (lock not held)
   ReqState state = ReqState::Queued;
@@ -133,11 +137,14 @@ struct fe_server {
   uint32_t* fine_count = nullptr;
   uint64_t fine_cap = 0;
   fe::TileShape shape{};
-  // image copies alternate between two streams (back-to-back host-to-device
-  // copies of a request pool move about 47 GB/s on one stream, 55 on two)
+  // image copies go to whichever of two streams has fewer bytes in flight
+  // (back-to-back host-to-device copies of a request pool move about 47 GB/s
+  // on one stream, 55 on two; a small image is not queued behind a large one
+  // while the other stream is free)
   static constexpr int kCopyStreams = 2;
   hipStream_t compute = nullptr, copy[kCopyStreams] = {nullptr, nullptr};
-  int next_copy = 0;
+  int next_copy = 0;                     // tie break between equally loaded streams
+  size_t copy_pending[kCopyStreams] = {0, 0};   // bytes of Copying requests (worker thread only)
   uint8_t* dev_base = nullptr;           // byte arena memory
   uint4* staging = nullptr;              // tile arena: record slots
   uint64_t* masks = nullptr;             // tile arena: occupancy
@@ -255,8 +262,12 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
   std::vector<char> ok(adm.size(), 0);
   for (size_t k = 0; k < adm.size(); ++k) {
     Request* r = adm[k];
-    const hipStream_t cs = s->copy[s->next_copy];
-    s->next_copy = (s->next_copy + 1) % fe_server::kCopyStreams;
+    int ci = s->next_copy;
+    for (int c = 0; c < fe_server::kCopyStreams; ++c)
+      if (s->copy_pending[c] < s->copy_pending[ci]) ci = c;
+    s->next_copy = (ci + 1) % fe_server::kCopyStreams;
+    const hipStream_t cs = s->copy[ci];
+    const size_t bytes = (size_t)r->pitch * r->h;
     // the image (the encode kernel writes every tile's mask whole)
     // rows of equal pitch on both sides are one linear copy (a pitched copy
     // is slower even when it covers the same bytes)
@@ -272,13 +283,38 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
                            hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipEventRecord(s->ev_copied[r->slot], cs);
     ok[k] = e == hipSuccess;
+    if (ok[k]) {
+      r->copy_stream = ci;
+      r->copy_bytes = bytes;
+      s->copy_pending[ci] += bytes;
+    }
   }
   lk.lock();
   for (size_t k = 0; k < adm.size(); ++k) {
-    if (ok[k]) adm[k]->state = ReqState::Running;
+    if (ok[k]) adm[k]->state = ReqState::Copying;
     else fail_request(adm[k]);
   }
   return true;
+}
+
+// Requests whose image copy has completed become Running, so that a step
+// never waits on a copy still in flight (a step holding a large image's
+// first blocks would otherwise hold back every request in it).  Lock held.
+// Returns true on any change.
+bool copied(fe_server* s) {
+  bool any = false;
+  for (Request* r : s->active) {
+    if (r->state != ReqState::Copying) continue;
+    const hipError_t q = hipEventQuery(s->ev_copied[r->slot]);
+    if (q == hipErrorNotReady) continue;
+    s->copy_pending[r->copy_stream] -= r->copy_bytes;
+    r->copy_stream = -1;
+    r->copy_bytes = 0;
+    if (q == hipSuccess) r->state = ReqState::Running;
+    else fail_request(r);
+    any = true;
+  }
+  return any;
 }
 
 // One step: a single launch over up to step_blocks blocks.  Returns true if
@@ -482,6 +518,7 @@ void worker_main(fe_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     bool progress = admit(s, lk);
+    progress |= copied(s);
     progress |= run_step(s, lk);
     const size_t before = s->completions.size();
     progress |= finish(s);
