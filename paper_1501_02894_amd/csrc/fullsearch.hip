@@ -314,20 +314,27 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
       const double P = n * (double)gmax + al[k] + be[k] * dsd;
       const bool pass = dvalid && rv[k] && P > 0.0 && 64.0 * P * P * (1.0 + 0x1p-40) >= thr[k] * dq;
       if (pass) {
-        int e = 7;
-#pragma unroll
-        for (int j = 7; j >= 0; --j)
-          if (acc[f][8 * s + j] == gmax) e = j;
         const double P16 = 16.0 * P;
         int kk = (7.0 * dq < P16) ? 4 : 0;
         kk += ((double)(2 * kk + 3) * dq < P16) ? 2 : 0;
         kk += ((double)(2 * kk + 1) * dq < P16) ? 1 : 0;
-        if (kk == 0) e = 0;
         const double fv = (double)(kk * kk) * dq - (double)(16 * kk) * P;
-        const uint64_t key = cand_key((int64_t)fv, dom, e);
-        if (key < bk[k]) {
-          bk[k] = key;
-          thr[k] = -fv;
+        // Only a candidate at least as good as the threshold can lower the
+        // range's minimum key: the threshold is -f of a real candidate (this
+        // lane's best, or the key already published for the range), whose
+        // key any worse f exceeds.  So the isometry and the key are formed
+        // for those few alone.
+        if (fv <= -thr[k]) {
+          int e = 7;
+#pragma unroll
+          for (int j = 7; j >= 0; --j)
+            if (acc[f][8 * s + j] == gmax) e = j;
+          if (kk == 0) e = 0;
+          const uint64_t key = cand_key((int64_t)fv, dom, e);
+          if (key < bk[k]) {
+            bk[k] = key;
+            thr[k] = -fv;
+          }
         }
       }
     }
@@ -610,10 +617,14 @@ hipError_t fs_search(const FsPlan& pl, const uint8_t* img, uint32_t w, uint32_t 
                      const uint8_t* planes, const uint32_t* sd, const double* qd, const uint32_t* xy, uint32_t R,
                      uint8_t* frag, uint32_t* sr, double* alpha, double* beta, uint64_t* best, hipStream_t s) {
   if (R == 0) return hipSuccess;
+  // A fragments per wave: two at B = 16 (152 VGPRs, three waves per SIMD);
+  // one at B = 8 and 4, whose epilogue is long against their short MFMA
+  // chains, so that eight waves per SIMD hide its latency (60 and 54 VGPRs;
+  // on C2 99 and 92 us against 134 and 115 us with four fragments)
   switch (pl.B) {
     case 16: return fs_search_t<16, 2>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
-    case 8: return fs_search_t<8, 4>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
-    case 4: return fs_search_t<4, 4>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
+    case 8: return fs_search_t<8, 1>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
+    case 4: return fs_search_t<4, 1>(pl, img, w, h, stride, planes, sd, qd, xy, R, frag, sr, alpha, beta, best, s);
     default: return hipErrorInvalidValue;
   }
 }
