@@ -93,8 +93,9 @@ class Arena {
   size_t size_ = 0, used_ = 0, g_ = 1;
 };
 
-// Queued -> Copying (image copy issued) -> Running (copy complete: steps take
-// its blocks) -> Ordering (last block launched) -> Done / Failed.
+// Queued -> Copying (a large image's copy issued) -> Running (steps take its
+// blocks; a small image's request goes there at once) -> Ordering (last
+// block launched) -> Done / Failed.
 enum class ReqState { Queued, Copying, Running, Ordering, Done, Failed };
 
 struct Request {
@@ -145,6 +146,7 @@ struct fe_server {
   hipStream_t compute = nullptr, copy[kCopyStreams] = {nullptr, nullptr};
   int next_copy = 0;                     // tie break between equally loaded streams
   size_t copy_pending[kCopyStreams] = {0, 0};   // bytes of Copying requests (worker thread only)
+  static constexpr size_t kDirectCopyBytes = 1u << 20;   // up to this, a request need not wait for its copy
   uint8_t* dev_base = nullptr;           // byte arena memory
   uint4* staging = nullptr;              // tile arena: record slots
   uint64_t* masks = nullptr;             // tile arena: occupancy
@@ -268,6 +270,10 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
     s->next_copy = (ci + 1) % fe_server::kCopyStreams;
     const hipStream_t cs = s->copy[ci];
     const size_t bytes = (size_t)r->pitch * r->h;
+    // a small copy on a stream with no large one ahead of it is done within
+    // tens of microseconds: its request joins the next step at once (the
+    // step waits on the copy's event on the device); the others are polled
+    const bool gated = bytes > fe_server::kDirectCopyBytes || s->copy_pending[ci] > 0;
     // the image (the encode kernel writes every tile's mask whole)
     // rows of equal pitch on both sides are one linear copy (a pitched copy
     // is slower even when it covers the same bytes)
@@ -283,7 +289,7 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
                            hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipEventRecord(s->ev_copied[r->slot], cs);
     ok[k] = e == hipSuccess;
-    if (ok[k]) {
+    if (ok[k] && gated) {
       r->copy_stream = ci;
       r->copy_bytes = bytes;
       s->copy_pending[ci] += bytes;
@@ -291,16 +297,16 @@ bool admit(fe_server* s, std::unique_lock<std::mutex>& lk) {
   }
   lk.lock();
   for (size_t k = 0; k < adm.size(); ++k) {
-    if (ok[k]) adm[k]->state = ReqState::Copying;
+    if (ok[k]) adm[k]->state = adm[k]->copy_stream >= 0 ? ReqState::Copying : ReqState::Running;
     else fail_request(adm[k]);
   }
   return true;
 }
 
-// Requests whose image copy has completed become Running, so that a step
-// never waits on a copy still in flight (a step holding a large image's
-// first blocks would otherwise hold back every request in it).  Lock held.
-// Returns true on any change.
+// Requests whose polled image copy has completed become Running, so that no
+// step waits on a large copy still in flight (a step holding a 16 Mpx
+// image's first blocks would otherwise hold back every request in it for
+// the copy's 0.3-0.7 ms).  Lock held.  Returns true on any change.
 bool copied(fe_server* s) {
   bool any = false;
   for (Request* r : s->active) {
