@@ -519,6 +519,26 @@ bool finish(fe_server* s) {
   return any;
 }
 
+// The first host-to-device copy of a size class on a stream has taken
+// 7-11 ms here (the runtime sets up that copy path on first use), once per
+// server; a step that met it held back every request in flight.  Creation
+// takes them instead: sizes from 64 B up by factors of 4, for the
+// descriptor upload on the compute stream and for image copies on the
+// copy streams.  The copied bytes are placeholders that nothing reads.
+bool warm_transfers(fe_server* s, size_t desc_max, size_t image_max) {
+  hipError_t e = hipSuccess;
+  for (size_t n = 64;; n *= 4) {
+    if (n <= 4 * desc_max)
+      e = hipMemcpyAsync(s->d_desc[0], s->h_desc[0], std::min(n, desc_max), hipMemcpyHostToDevice, s->compute);
+    for (int c = 0; e == hipSuccess && c < fe_server::kCopyStreams; ++c)
+      e = hipMemcpyAsync(s->dev_base, s->host_base, std::min(n, image_max), hipMemcpyHostToDevice, s->copy[c]);
+    if (e != hipSuccess || (n >= desc_max && n >= image_max)) break;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->compute);
+  for (int c = 0; e == hipSuccess && c < fe_server::kCopyStreams; ++c) e = hipStreamSynchronize(s->copy[c]);
+  return e == hipSuccess;
+}
+
 void worker_main(fe_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -610,6 +630,11 @@ fe_status fe_server_create(int device, const fe_params* p, size_t hbm_budget, si
   if (!ok) {
     fe_server_destroy(s);
     return fe::fail(FE_ERR_OOM, "server allocation failed");
+  }
+  if (!warm_transfers(s, desc_bytes(step_blocks, 2 * (size_t)step_blocks),
+                      std::min<size_t>({byte_budget, host_budget, (size_t)64 << 20}))) {
+    fe_server_destroy(s);
+    return fe::fail(FE_ERR_DEVICE, "server stream set-up failed");
   }
   s->dev_arena.reset(byte_budget, 256);
   // tile slots are handed out in whole blocks of the tile shape
