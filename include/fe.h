@@ -455,6 +455,9 @@ fe_status fe_autotune(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_imgs,
  * A worker thread drives the steps.  The ordering kernel writes a finished
  * request's records straight into its pinned result buffer, which stays
  * reserved until the request is fetched: callers should poll promptly.
+ * Creation also makes one host-to-device copy of each size class on each
+ * of the server's streams (tens of milliseconds in all), so that no step
+ * pays the runtime's set-up of a copy path; FE_ERR_DEVICE if that fails.
  *
  * fe_server_submit copies the host image (W x H, row pitch `stride`) into
  * pinned staging and queues it; the caller may reuse h_img on return.
