@@ -13,9 +13,12 @@
 
 struct fe_ctx {
   int device = 0;
-  hipEvent_t table_ready = nullptr;   // last copy out of h_table finished
-  fe::ImgDev* h_table = nullptr;      // pinned staging of the image table
-  size_t h_table_n = 0;
+  // pinned staging of the image table, two buffers used in turn, so that a
+  // new table waits only for the copy out of the table before the last
+  hipEvent_t table_ready[2] = {nullptr, nullptr};   // copy out of h_table[k] finished
+  fe::ImgDev* h_table[2] = {nullptr, nullptr};
+  size_t h_table_n[2] = {0, 0};
+  int table_cur = 0;                  // the buffer the device table was copied from
   size_t table_slots = 0;             // size of the table on the device (0: none)
   uint64_t table_gen = 0;             // bumped whenever the device table changes
   bool blocks_valid = false;          // block descriptors built from ...
@@ -209,29 +212,33 @@ size_t table_words(const fe::ImgDev* src, size_t n, uint64_t tiles, std::vector<
 fe_status upload_table(fe_ctx* ctx, const fe::ImgDev* src, size_t n, uint64_t tiles, hipStream_t s) {
   std::vector<fe::ImgDev> host;
   const size_t slots = table_words(src, n, tiles, host);
-  if (ctx->table_slots == slots && ctx->d_table && ctx->h_table &&
-      memcmp(ctx->h_table, host.data(), slots * sizeof(fe::ImgDev)) == 0) {
+  const int cur = ctx->table_cur;
+  if (ctx->table_slots == slots && ctx->d_table && ctx->h_table[cur] &&
+      memcmp(ctx->h_table[cur], host.data(), slots * sizeof(fe::ImgDev)) == 0) {
     // already on the device; order this stream after its copy
-    FE_HIP(hipStreamWaitEvent(s, ctx->table_ready, 0), "wait for table copy");
+    FE_HIP(hipStreamWaitEvent(s, ctx->table_ready[cur], 0), "wait for table copy");
     return FE_OK;
   }
-  FE_HIP(hipEventSynchronize(ctx->table_ready), "wait for previous table copy");
-  if (slots > ctx->h_table_n) {
-    if (ctx->h_table) (void)hipHostFree(ctx->h_table);
-    ctx->h_table = nullptr;
-    ctx->h_table_n = 0;
-    FE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_table), slots * sizeof(fe::ImgDev), hipHostMallocDefault),
+  // the other buffer: its copy (the table before the last) is done long ago
+  const int nb = cur ^ 1;
+  FE_HIP(hipEventSynchronize(ctx->table_ready[nb]), "wait for an earlier table copy");
+  if (slots > ctx->h_table_n[nb]) {
+    if (ctx->h_table[nb]) (void)hipHostFree(ctx->h_table[nb]);
+    ctx->h_table[nb] = nullptr;
+    ctx->h_table_n[nb] = 0;
+    FE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_table[nb]), slots * sizeof(fe::ImgDev), hipHostMallocDefault),
            "pinned image table");
-    ctx->h_table_n = slots;
+    ctx->h_table_n[nb] = slots;
   }
   ctx->table_slots = 0;   // invalid until the copy is enqueued
   ++ctx->table_gen;
   fe_status st = ensure(ctx->d_table, ctx->d_table_n, slots, "device image table");
   if (st != FE_OK) return st;
-  memcpy(ctx->h_table, host.data(), slots * sizeof(fe::ImgDev));
-  FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table, slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
+  memcpy(ctx->h_table[nb], host.data(), slots * sizeof(fe::ImgDev));
+  FE_HIP(hipMemcpyAsync(ctx->d_table, ctx->h_table[nb], slots * sizeof(fe::ImgDev), hipMemcpyHostToDevice, s),
          "image table copy");
-  FE_HIP(hipEventRecord(ctx->table_ready, s), "table event");
+  FE_HIP(hipEventRecord(ctx->table_ready[nb], s), "table event");
+  ctx->table_cur = nb;
   ctx->table_slots = slots;
   return FE_OK;
 }
@@ -570,7 +577,8 @@ fe_status fe_create(int device, fe_ctx** out) {
   DeviceGuard g(device);
   fe_ctx* c = new fe_ctx();
   c->device = device;
-  hipError_t e1 = hipEventCreateWithFlags(&c->table_ready, hipEventDisableTiming);
+  hipError_t e1 = hipEventCreateWithFlags(&c->table_ready[0], hipEventDisableTiming);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&c->table_ready[1], hipEventDisableTiming);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&c->blocks_ready, hipEventDisableTiming);
   hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&c->h_scalars), 64, hipHostMallocDefault);
   hipError_t e3 = hipMalloc(reinterpret_cast<void**>(&c->flags), 64);
@@ -591,9 +599,11 @@ void fe_destroy(fe_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
-  if (c->table_ready) (void)hipEventDestroy(c->table_ready);
+  for (int k = 0; k < 2; ++k) {
+    if (c->table_ready[k]) (void)hipEventDestroy(c->table_ready[k]);
+    if (c->h_table[k]) (void)hipHostFree(c->h_table[k]);
+  }
   if (c->blocks_ready) (void)hipEventDestroy(c->blocks_ready);
-  if (c->h_table) (void)hipHostFree(c->h_table);
   if (c->h_scalars) (void)hipHostFree(c->h_scalars);
   (void)hipFree(c->d_table);
   (void)hipFree(c->staging);
