@@ -519,12 +519,12 @@ bool finish(fe_server* s) {
   return any;
 }
 
-// The first host-to-device copy of a size class on a stream has taken
-// 7-11 ms here (the runtime sets up that copy path on first use), once per
-// server; a step that met it held back every request in flight.  Creation
-// takes them instead: sizes from 64 B up by factors of 4, for the
-// descriptor upload on the compute stream and for image copies on the
-// copy streams.  The copied bytes are placeholders that nothing reads.
+// The first host-to-device copy of a size class on a new stream has been
+// measured at 7-11 ms (the runtime sets up that copy path on first use), once
+// per server; a step that met it held back every request in flight.
+// Creation takes them instead: sizes from 64 B up by factors of 4, for the
+// descriptor upload on the compute stream and for image copies on the copy
+// streams.  The copied bytes are placeholders that nothing reads.
 bool warm_transfers(fe_server* s, size_t desc_max, size_t image_max) {
   hipError_t e = hipSuccess;
   for (size_t n = 64;; n *= 4) {
