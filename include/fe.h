@@ -276,7 +276,9 @@ fe_status fe_encode_noalloc(fe_ctx* ctx, const uint8_t* d_img, uint32_t width, u
  * Recorded batch encode (a HIP graph).  fe_plan_create validates the batch
  * as fe_encode_batch does, allocates the plan's own scratch (record slots
  * and masks for every top tile, block descriptors, ordering scratch),
- * uploads the image table and records the launch sequence once.
+ * uploads the image table, builds the workgroup block descriptors (they
+ * depend only on the images' addresses and sizes) and records the launch
+ * sequence once.
  * fe_plan_launch replays it on `stream`: the images are re-read in place
  * (their contents may change between launches, their addresses and sizes
  * may not), and the stream and offsets are written to d_out / d_offsets as

@@ -1047,10 +1047,11 @@ std::vector<hipGraphNode_t> chain_of(hipGraph_t g) {
 }
 
 // Splice event-record nodes into a copy of the plan's chain
-// [prep, encode, order...]: own[0] between prep and encode, own[1] and
-// own[2] between encode and the first ordering kernel, own[3] after the
-// last.  Instantiates the copy.  Returns false (and leaves the plan
-// untouched) if any step fails.
+// [[zero count], encode, [2 x 2 level], order...]: own[0] just before the
+// encode kernel (after the count's clearing, or as a root), own[1] and
+// own[2] between the encode kernels and the first ordering kernel, own[3]
+// after the last.  Instantiates the copy.  Returns false (and leaves the
+// plan untouched) if any step fails.
 bool add_timing_nodes(fe_plan* pl, size_t i_enc, size_t i_ord) {
   hipGraph_t g = nullptr;
   if (hipGraphClone(&g, pl->graph) != hipSuccess) return false;
@@ -1059,10 +1060,14 @@ bool add_timing_nodes(fe_plan* pl, size_t i_enc, size_t i_ord) {
     // chain positions: the encode kernels are c[i_enc] .. c[i_ord - 1], the
     // ordering kernels c[i_ord] ..
     std::vector<hipGraphNode_t> c = chain_of(g);
-    if (i_enc == 0 || i_ord <= i_enc || c.size() <= i_ord) break;
-    hipGraphNode_t prep = c[i_enc - 1], enc = c[i_enc], enc_end = c[i_ord - 1], ord = c[i_ord], last = c.back();
+    if (i_ord <= i_enc || c.size() <= i_ord) break;
+    hipGraphNode_t enc = c[i_enc], enc_end = c[i_ord - 1], ord = c[i_ord], last = c.back();
     hipGraphNode_t n[4] = {};
-    if (hipGraphAddEventRecordNode(&n[0], g, &prep, 1, pl->own[0]) != hipSuccess) break;
+    if (i_enc > 0) {
+      if (hipGraphAddEventRecordNode(&n[0], g, &c[i_enc - 1], 1, pl->own[0]) != hipSuccess) break;
+    } else {
+      if (hipGraphAddEventRecordNode(&n[0], g, nullptr, 0, pl->own[0]) != hipSuccess) break;
+    }
     if (hipGraphAddDependencies(g, &n[0], &enc, 1) != hipSuccess) break;
     if (hipGraphAddEventRecordNode(&n[1], g, &enc_end, 1, pl->own[1]) != hipSuccess) break;
     if (hipGraphAddEventRecordNode(&n[2], g, &enc_end, 1, pl->own[2]) != hipSuccess) break;
@@ -1123,14 +1128,22 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     return hip_fail(e, "plan allocation");
   }
   pl->ctx = ctx;
+  // The block descriptors depend only on the images' addresses and sides,
+  // which a plan fixes: they are built once, here, not in every replay.
+  e = fe::launch_block_prep(pl->d_table, n_imgs, wgs, geo.bmax, geo.shape.gx, geo.shape.gy, pl->blocks, pl->capture);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->capture);
+  if (e != hipSuccess) {
+    fe_plan_destroy(pl);
+    return hip_fail(e, "plan block descriptors");
+  }
   // record the launch sequence once; replays re-read the images in place.
-  // Chain: prep, [zero count], encode, [2 x 2 level], ordering; the count
-  // is cleared by a kernel, not a memset node.
+  // Chain: [zero count], encode, [2 x 2 level], ordering; the count is
+  // cleared by a kernel, not a memset node.
   e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const fe::EncodeBufs b{pl->d_table, pl->blocks, pl->staging, pl->masks, pl->chunk_sum, pl->chunk_base,
                            pl->fine_list, pl->fine_count};
-    const fe_status ls = fe::encode_launch(nullptr, geo, b, n_imgs, p, true, d_out, cap, d_offsets, pl->capture);
+    const fe_status ls = fe::encode_launch(nullptr, geo, b, n_imgs, p, false, d_out, cap, d_offsets, pl->capture);
     e = hipStreamEndCapture(pl->capture, &pl->graph);
     if (ls != FE_OK && e == hipSuccess) e = hipErrorLaunchFailure;
   }
@@ -1138,12 +1151,12 @@ fe_status fe_plan_create(fe_ctx* ctx, const fe_image_desc* h_imgs, uint32_t n_im
     fe_plan_destroy(pl);
     return hip_fail(e, "plan capture");
   }
-  // The capture is a chain: prep, [zero count], encode, [2 x 2 level], then
-  // the ordering kernels.  If timing is on, a copy of it gets event-record
-  // nodes before and after the encode kernels and after the last ordering
-  // kernel; if that fails, or timing is off, the plain chain is used and
-  // launches are not timed.
-  pl->timed = ctx->timing && (ext ? add_timing_nodes(pl, 2, 4) : add_timing_nodes(pl, 1, 2));
+  // The capture is a chain: [zero count], encode, [2 x 2 level], then the
+  // ordering kernels.  If timing is on, a copy of it gets event-record nodes
+  // before and after the encode kernels and after the last ordering kernel;
+  // if that fails, or timing is off, the plain chain is used and launches
+  // are not timed.
+  pl->timed = ctx->timing && (ext ? add_timing_nodes(pl, 1, 3) : add_timing_nodes(pl, 0, 1));
   if (!pl->timed) {
     e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
