@@ -254,14 +254,25 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
   }
   const double n = (double)(B * B);
   const uint32_t xcol = x0 + (uint32_t)col;
+  const bool dvalid = xcol < ncols;
+  const uint32_t u = 2 * xcol + p;
+  // The domain sums of strip t + 1 are loaded while strip t is searched, so
+  // that no strip waits for its own; a lane without a domain there reads
+  // domain 0 and ignores it.
+  const uint32_t dom0 = dvalid ? (2 * t0 + q) * g.nu + u : 0u;
+  uint32_t sd_next = sd[dom0];
+  double qd_next = qd[dom0];
   for (int t = 0; t < kStripsPerBlock; ++t) {
     const uint32_t trow = t0 + (uint32_t)t;
     if (trow >= nrows) break;                       // uniform over the workgroup
-    const bool dvalid = xcol < ncols;
-    const uint32_t u = 2 * xcol + p, v = 2 * trow + q;
+    const uint32_t v = 2 * trow + q;
     const uint32_t dom = v * g.nu + u;
-    const double dsd = dvalid ? (double)sd[dom] : 0.0;
-    const double dq = dvalid ? qd[dom] : 0.0;
+    const double dsd = dvalid ? (double)sd_next : 0.0;
+    const double dq = dvalid ? qd_next : 0.0;
+    const bool more = dvalid && t + 1 < kStripsPerBlock && trow + 1 < nrows;
+    const uint32_t dom_next = more ? dom + 2 * g.nu : 0u;
+    sd_next = sd[dom_next];
+    qd_next = qd[dom_next];
     v16i acc[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
