@@ -195,20 +195,23 @@ __global__ __launch_bounds__(256) void fs_gemm_kernel(FsGeo g, const uint8_t* fr
   if (t0 >= nrows || x0 >= ncols) return;
   const uint8_t* plane = g.planes + (size_t)cls * g.pitch * g.prow;
   // stage plane rows t0 .. t0 + LROWS - 1, columns x0 .. x0 + LP - 1, in
-  // four copies shifted by 0..3 bytes (the last words of a row read up to 3
-  // bytes past it, inside the plane's padded pitch, and are never used)
-  for (int i = tid; i < 4 * C::LROWS * (C::LP / 4); i += 256) {
-    const int k = i / (C::LROWS * (C::LP / 4));
-    const int i2 = i - k * (C::LROWS * (C::LP / 4));
-    const int r = i2 / (C::LP / 4), c4 = i2 - r * (C::LP / 4);
-    uint32_t v = 0;
+  // four copies shifted by 0..3 bytes: a lane reads two aligned words of a
+  // row (the pitch and x0 are multiples of 4) and forms the word of every
+  // copy from them.  The last words of a row read up to 7 bytes past it,
+  // inside the plane's padded pitch, and are never used.
+  for (int i = tid; i < C::LROWS * (C::LP / 4); i += 256) {
+    const int r = i / (C::LP / 4), c4 = i - r * (C::LP / 4);
+    uint32_t w0 = 0, w1 = 0;
     const uint32_t row = t0 + (uint32_t)r;
     if (row < g.prow) {
-      const uint8_t* s = plane + (size_t)row * g.pitch + x0 + 4 * c4 + k;
-      v = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16) | ((uint32_t)s[3] << 24);
+      const uint32_t* s = reinterpret_cast<const uint32_t*>(plane + (size_t)row * g.pitch + x0) + c4;
+      w0 = s[0];
+      w1 = s[1];
     }
     // staged centred: d - 128 == d ^ 0x80 as int8
-    s_pl[k * C::CW + r * (C::LP / 4) + c4] = v ^ 0x80808080u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      s_pl[k * C::CW + r * (C::LP / 4) + c4] = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)k) ^ 0x80808080u;
   }
   __syncthreads();
   // this lane's copy and word column: every window row starts word-aligned
